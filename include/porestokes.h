@@ -1,0 +1,227 @@
+/*
+ * porestokes.h -- C ABI of the MI355X (gfx950) pseudo-unsteady Stokes
+ * permeability solver.
+ *
+ * Method (Krach, Ruf, Steeb, "POREMAPS", arXiv 2407.19868):
+ *   - binary voxel image in, solid/pore (§5.1; here: nonzero byte = solid);
+ *   - staggered MAC grid, face velocities u, v, w and cell pressure p (§4 "Grid");
+ *   - no-slip / no-penetration at voxel faces touching solid (§4), second
+ *     derivatives across the flow from the neighbourhood cases of App. B;
+ *   - artificial-compressibility pseudo-time stepping of the nondimensional
+ *     equations (§3, App. A), velocity then pressure each sweep (Algorithm 1);
+ *   - drive: a mean pressure gradient G along the load axis, periodic
+ *     fluctuation p~ (§4 "Simulation parametrization", Fig. 2);
+ *   - Darcy: k_{i,j} = mu q_i / h_j from three load cases (§4 eq. darcy,
+ *     eq. cases_pressure; App. C), off-diagonals averaged for k_sym (App. C).
+ *
+ * Conventions shared by every call
+ *   Layout:     every 3-D array is [nz][ny][nx], x fastest, dense, no padding.
+ *               u[c] is the x-face between cells c - e_x and c (likewise v, w);
+ *               p[c] is the cell-centre pressure fluctuation p~.
+ *               All domains are periodic on all three axes.
+ *   Pointers:   "device" pointers are HIP device memory of the context's GPU
+ *               (e.g. torch tensor data_ptr()); "host" pointers are CPU memory.
+ *               The caller owns every pointer it passes; the library never
+ *               frees them.  Device field pointers must be 8-byte aligned.
+ *   Streams:    `stream` is a hipStream_t (NULL = default stream).  All device
+ *               work of a call is ordered on it.  Calls that return numbers on
+ *               the host (solve, tensor, batch, residual) synchronise that
+ *               stream before returning; pm_preprocess, pm_face_codes and
+ *               pm_iterate only enqueue work.
+ *   Errors:     every call returns pm_status.  Argument errors are detected
+ *               before any device write.  The text of the last error is kept
+ *               per context (pm_last_error).  No C++ exception crosses the ABI.
+ *   Threads:    one context per host thread.
+ *   Units:      fields are in the solver's nondimensional units: lengths in
+ *               voxels, nu = 1/re, drive G (default 1 per voxel).  k is
+ *               returned in physical units: k[vx^2] * voxel_size^2.  The
+ *               viscosity mu cancels from k (the paper fixes Re); it only
+ *               scales a physical velocity, v_phys = v * voxel_size^2 / (mu re)
+ *               per unit applied pressure gradient.
+ */
+#ifndef PORESTOKES_H
+#define PORESTOKES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PM_OK = 0,             /* converged / success                                   */
+    PM_ERR_ARG = 1,        /* invalid argument; nothing was written                 */
+    PM_ERR_OOM = 2,        /* device allocation failed or exceeds the context cap   */
+    PM_ERR_DEVICE = 3,     /* HIP runtime error                                     */
+    PM_NOT_CONVERGED = 4,  /* max_sweeps reached; results are those of the last check */
+    PM_DIVERGED = 5,       /* non-finite residual or r > 1e3 * min(r)               */
+    PM_ERR_NO_FLOW = 6     /* no solid voxel, or no fluid face normal to the load axis */
+} pm_status;
+
+typedef enum {
+    PM_FP64 = 0,    /* FP64 fields and arithmetic                                      */
+    PM_FP32 = 1,    /* FP32 fields and arithmetic, FP64 reductions                     */
+    PM_FP32_DC = 2  /* FP32 phase until the residual stalls, then FP64 defect
+                       correction from the promoted state until tol                    */
+} pm_precision;
+
+typedef enum {
+    PM_KERNEL_AUTO = 0,   /* fused kernel, tile from the autotuner / defaults         */
+    PM_KERNEL_FUSED = 1,  /* one pass per sweep: pressure of sweep n and velocity of
+                             sweep n+1 fused, LDS-staged tiles streamed along z       */
+    PM_KERNEL_SIMPLE = 2  /* two passes per sweep (velocity, pressure), one thread per
+                             cell, no LDS; the same per-face arithmetic               */
+} pm_kernel;
+
+/* Solver parameters.  pm_params_default fills the paper's values (§4). */
+typedef struct {
+    double re;          /* Reynolds number; nu = 1/re.          default 0.01 (§4)    */
+    double c2;          /* artificial compressibility c*^2.     default 1.5e6 (§4)   */
+    double dt;          /* pseudo-time step.                    default 2^-12        */
+    double tol;         /* stop when r < tol (or eps_q < tol).  default 1e-8         */
+    double drive;       /* mean pressure gradient G per voxel.  default 1 (§4)       */
+    int64_t max_sweeps; /*                                      default 10^7         */
+    int32_t check_every;/* residual check every M sweeps.       default 100          */
+    int32_t precision;  /* pm_precision.                        default PM_FP64      */
+    int32_t stop_rule;  /* 0: r < tol; 1: eps_q < tol (relative change of |q|
+                           between checks, the paper's criterion §7.1)              */
+    int32_t warm_start; /* 1: start from the fields passed in (else from rest)       */
+    int32_t kernel;     /* pm_kernel.                           default AUTO         */
+    int32_t tile_x;     /* fused-kernel tile override (0 = auto): 32 or 64           */
+    int32_t tile_y;     /* fused-kernel tile override (0 = auto): 4, 8 or 16         */
+    int32_t zchunk;     /* planes per workgroup along z (0 = auto)                   */
+    int32_t reserved[4];
+} pm_params;
+
+/* Residual history: one record per check.  Host arrays of length cap owned by
+ * the caller (q has 3*cap entries); n is set to the number of records written
+ * (at most cap; later records are dropped). */
+typedef struct {
+    int64_t cap;
+    int64_t n;
+    int64_t *sweep;  /* sweep count of the record                                  */
+    double *resid;   /* r = sqrt(S_F + S_D) / (G sqrt(N_f))                         */
+    double *eps_q;   /* | |q_n| - |q_prev| | / |q_n|  (inf at the first record)      */
+    double *q;       /* mean face velocity q_x, q_y, q_z of the state (3 per record)  */
+} pm_history;
+
+typedef struct pm_ctx pm_ctx;
+
+/* Fill *p with the defaults listed in pm_params. */
+void pm_params_default(pm_params *p);
+
+/* Text for a status code (static storage). */
+const char *pm_status_string(pm_status s);
+
+/* Create a context on HIP device `hip_device`.  mem_cap_bytes bounds the
+ * context's own device allocations (0 = no bound); a call that would exceed
+ * it returns PM_ERR_OOM.  *out receives the context. */
+pm_status pm_create(int hip_device, size_t mem_cap_bytes, pm_ctx **out);
+
+/* Free the context and its device scratch.  NULL is ignored. */
+void pm_destroy(pm_ctx *ctx);
+
+/* Message of the last error on this context ("" if none).  Valid until the next call. */
+const char *pm_last_error(const pm_ctx *ctx);
+
+/* Device bytes currently held by the context. */
+size_t pm_mem_used(const pm_ctx *ctx);
+
+/*
+ * Face flags ("Evaluate neighborhood", Algorithm 1; §4): a face is solid iff
+ * either adjacent voxel is solid.  mask: device uint8 [nz][ny][nx].
+ * bits: device uint32 [3][nz][ny][ceil(nx/32)]; plane k holds the k-faces,
+ * bit b of word w is x = 32 w + b; padding bits are 0.
+ */
+pm_status pm_preprocess(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny,
+                        int64_t nz, uint32_t *bits);
+
+/*
+ * Per-cell stencil codes used by the sweep (App. B neighbourhood cases).
+ * codes: device uint32 [nz][ny][nx].  For component k (bit offset 8 k):
+ *   bits 0-2  code along the first perpendicular axis (x->y, y->x, z->x),
+ *   bits 3-5  code along the second perpendicular axis (x->z, y->z, z->y),
+ *   bit  6    face solid.
+ * A 3-bit code is L | R<<1 | F<<2 with L / R = solid face at offset -1 / +1
+ * (wall half a voxel away) and F = solid face at offset +2 (if only L) or -2
+ * (if only R), i.e. a wall 3/2 voxels away.  Cases: none = 6, L = 4, R = 5,
+ * L+F = 2, R+F = 3, L+R = 1.
+ */
+pm_status pm_face_codes(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny,
+                        int64_t nz, uint32_t *codes);
+
+/*
+ * Run exactly `count` sweeps on the state (u, v, w, p) in place, load axis
+ * `axis` (0 x, 1 y, 2 z).  Fields are device arrays of nx*ny*nz doubles
+ * (params->precision PM_FP64) or floats (PM_FP32); PM_FP32_DC is rejected.
+ * Faces touching solid are set to 0 first.  Enqueue only.
+ */
+pm_status pm_iterate(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny,
+                     int64_t nz, int axis, const pm_params *params, void *u, void *v, void *w,
+                     void *p, int64_t count);
+
+/*
+ * Residual sums of a state, computed in FP64 on the GPU: out[0] = S_F (sum of
+ * squared momentum residuals over fluid faces), out[1] = S_D (sum of squared
+ * nu*div v over cells), out[2..4] = sums of u, v, w over all faces.  Fields as
+ * in pm_iterate.  out is a host array of 5 doubles.  Synchronises the stream.
+ */
+pm_status pm_residual(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny,
+                      int64_t nz, int axis, const pm_params *params, const void *u,
+                      const void *v, const void *w, const void *p, double out[5]);
+
+/*
+ * One load case (Algorithm 1; eq. cases_pressure): iterate from rest (or from
+ * the given fields with warm_start) until the stop rule, with checks every
+ * check_every sweeps.  Fields: device arrays of nx*ny*nz doubles (PM_FP64,
+ * PM_FP32_DC) or floats (PM_FP32); on return they hold the state at the last
+ * check.  hist: host, may be NULL.  k_col (host, 3 doubles): k_{i,axis} in
+ * voxel_size^2 units, i = x, y, z.  sweeps_done (host, may be NULL).
+ * Returns PM_OK, PM_NOT_CONVERGED, PM_DIVERGED, PM_ERR_NO_FLOW or an error.
+ */
+pm_status pm_solve(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny,
+                   int64_t nz, double voxel_size, double mu, int axis, const pm_params *params,
+                   void *u, void *v, void *w, void *p, pm_history *hist, double k_col[3],
+                   int64_t *sweeps_done);
+
+/*
+ * Full tensor (§2 eq. 3dK; App. C): the three load cases x, y, z solved as one
+ * batch.  k (host, 9 doubles, row-major k[i*3+j] = k_ij, column j from load
+ * axis j) and k_sym = (k + k^T)/2 (host, 9).  hist: host array of 3 histories
+ * or NULL.  sweeps: host array of 3 or NULL.  Fields are kept internally.
+ */
+pm_status pm_tensor(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny,
+                    int64_t nz, double voxel_size, double mu, const pm_params *params,
+                    double k[9], double k_sym[9], pm_history *hist, int64_t sweeps[3]);
+
+/* One instance of a batch: a (mask, load axis) solve. */
+typedef struct {
+    const uint8_t *mask;   /* device uint8 [nz][ny][nx]                              */
+    int64_t nx, ny, nz;
+    double voxel_size, mu;
+    int32_t axis;
+    int32_t pad;
+    void *u, *v, *w, *p;   /* device fields (as in pm_solve), or all NULL: internal  */
+    pm_history *hist;      /* host, may be NULL                                      */
+    double k_col[3];       /* out                                                    */
+    int64_t sweeps;        /* out                                                    */
+    int32_t status;        /* out: pm_status of this instance                        */
+    int32_t pad2;
+} pm_instance;
+
+/*
+ * Batched solves (many masks of uneven sizes and load axes, e.g. clogging or
+ * compression series and the three load cases of each): every sweep of all
+ * active instances is one launch; an instance that meets its stop rule stops
+ * being swept while the others continue.  Each instance gets its own status;
+ * the call returns the worst one (error > DIVERGED > NO_FLOW > NOT_CONVERGED > OK).
+ */
+pm_status pm_solve_batch(pm_ctx *ctx, void *stream, pm_instance *inst, int32_t n,
+                         const pm_params *params);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PORESTOKES_H */

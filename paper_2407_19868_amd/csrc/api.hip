@@ -1,0 +1,934 @@
+// porestokes C ABI: contexts, argument checking, the solve loop (Algorithm 1
+// without MPI), Darcy reduction (App. C) and batching.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+#include "porestokes.h"
+
+using namespace ps;
+
+struct pm_ctx {
+    int dev = 0;
+    size_t cap = 0, used = 0;
+    std::string err;
+    std::unordered_map<void *, size_t> allocs;
+    double *h_sums = nullptr;  // pinned host buffer for reduced sums
+    size_t h_sums_n = 0;
+    std::map<std::string, std::vector<int>> tune;  // autotuned (tile_x, tile_y, zc) per shape key
+    bool tune_loaded = false;
+};
+
+namespace {
+
+pm_status fail(pm_ctx *ctx, pm_status s, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return s;
+}
+
+#define PM_HIP(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return fail(ctx, PM_ERR_DEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),     \
+                        __FILE__, __LINE__);                                                           \
+    } while (0)
+
+#define PM_TRY(expr)                                                                                   \
+    do {                                                                                               \
+        pm_status s_ = (expr);                                                                         \
+        if (s_ != PM_OK) return s_;                                                                    \
+    } while (0)
+
+pm_status dalloc(pm_ctx *ctx, size_t bytes, void **out)
+{
+    *out = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (ctx->cap && ctx->used + bytes > ctx->cap)
+        return fail(ctx, PM_ERR_OOM, "device allocation of %zu bytes exceeds the context cap (%zu used of %zu)",
+                    bytes, ctx->used, ctx->cap);
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *out = nullptr;
+        return fail(ctx, PM_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    ctx->allocs[*out] = bytes;
+    ctx->used += bytes;
+    return PM_OK;
+}
+
+void dfree(pm_ctx *ctx, void *p)
+{
+    if (!p) return;
+    auto it = ctx->allocs.find(p);
+    if (it != ctx->allocs.end()) {
+        ctx->used -= it->second;
+        ctx->allocs.erase(it);
+    }
+    (void)hipFree(p);
+}
+
+// Device allocations owned by one call, released on every exit path.
+struct Scratch {
+    pm_ctx *ctx;
+    std::vector<void *> ptrs;
+    explicit Scratch(pm_ctx *c) : ctx(c) {}
+    ~Scratch()
+    {
+        for (void *p : ptrs) dfree(ctx, p);
+    }
+    pm_status get(size_t bytes, void **out)
+    {
+        pm_status s = dalloc(ctx, bytes, out);
+        if (s == PM_OK) ptrs.push_back(*out);
+        return s;
+    }
+};
+
+pm_status ensure_host_sums(pm_ctx *ctx, size_t n)
+{
+    if (ctx->h_sums_n >= n) return PM_OK;
+    if (ctx->h_sums) (void)hipHostFree(ctx->h_sums);
+    ctx->h_sums = nullptr;
+    ctx->h_sums_n = 0;
+    void *p = nullptr;
+    PM_HIP(hipHostMalloc(&p, n * sizeof(double), hipHostMallocDefault));
+    ctx->h_sums = (double *)p;
+    ctx->h_sums_n = n;
+    return PM_OK;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+pm_status check_dims(pm_ctx *ctx, int64_t nx, int64_t ny, int64_t nz)
+{
+    if (nx < 1 || ny < 1 || nz < 1) return fail(ctx, PM_ERR_ARG, "dims must be >= 1 (got %lld %lld %lld)",
+                                                 (long long)nx, (long long)ny, (long long)nz);
+    if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30) || nx * ny > 0x7fffffffLL ||
+        nx * ny * nz > (int64_t(1) << 40))
+        return fail(ctx, PM_ERR_ARG, "dims too large (%lld %lld %lld)", (long long)nx, (long long)ny,
+                    (long long)nz);
+    return PM_OK;
+}
+
+pm_status check_params(pm_ctx *ctx, const pm_params *p)
+{
+    if (!p) return fail(ctx, PM_ERR_ARG, "params is NULL");
+    if (!(p->re > 0) || !(p->c2 > 0) || !(p->dt > 0) || !(p->tol > 0) || !(p->drive > 0) ||
+        !std::isfinite(p->re) || !std::isfinite(p->c2) || !std::isfinite(p->dt) || !std::isfinite(p->drive))
+        return fail(ctx, PM_ERR_ARG, "re, c2, dt, tol and drive must be positive and finite");
+    if (p->check_every < 1) return fail(ctx, PM_ERR_ARG, "check_every must be >= 1");
+    if (p->max_sweeps < 0) return fail(ctx, PM_ERR_ARG, "max_sweeps must be >= 0");
+    if (p->precision < PM_FP64 || p->precision > PM_FP32_DC) return fail(ctx, PM_ERR_ARG, "bad precision");
+    if (p->stop_rule != 0 && p->stop_rule != 1) return fail(ctx, PM_ERR_ARG, "bad stop_rule");
+    if (p->kernel < PM_KERNEL_AUTO || p->kernel > PM_KERNEL_SIMPLE) return fail(ctx, PM_ERR_ARG, "bad kernel");
+    if ((p->tile_x || p->tile_y) && !fused_tile_supported(p->tile_x, p->tile_y))
+        return fail(ctx, PM_ERR_ARG, "unsupported tile %dx%d", p->tile_x, p->tile_y);
+    if (p->zchunk < 0) return fail(ctx, PM_ERR_ARG, "zchunk must be >= 0");
+    return PM_OK;
+}
+
+pm_status set_device(pm_ctx *ctx)
+{
+    PM_HIP(hipSetDevice(ctx->dev));
+    return PM_OK;
+}
+
+// ------------------------------------------------------------------ tiles
+
+struct TileCfg {
+    int tx = 64, ty = 8, zc = 32;
+};
+
+int auto_zc(int nx, int ny, int nz, int tx, int ty)
+{
+    const int64_t txy = (int64_t)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
+    // aim for >= 2048 workgroups (8 per CU) while keeping chunks long enough to
+    // amortise the 5-plane priming of the register window
+    int64_t zc = (int64_t)nz * txy / 2048;
+    zc = std::max<int64_t>(8, std::min<int64_t>(64, zc));
+    return (int)std::min<int64_t>(zc, nz);
+}
+
+TileCfg pick_tiles(pm_ctx *ctx, const pm_params *prm, int nx, int ny, int nz, Prec prec)
+{
+    TileCfg c;
+    auto it = ctx->tune.find(std::to_string(nx) + "x" + std::to_string(ny) + "x" + std::to_string(nz) +
+                             (prec == kF64 ? ":f64" : ":f32"));
+    if (it != ctx->tune.end() && it->second.size() == 3) {
+        c.tx = it->second[0];
+        c.ty = it->second[1];
+        c.zc = it->second[2];
+    } else {
+        c.tx = 64;
+        c.ty = 8;
+        c.zc = 0;
+    }
+    if (prm->tile_x && prm->tile_y) {
+        c.tx = prm->tile_x;
+        c.ty = prm->tile_y;
+    }
+    if (prm->zchunk > 0) c.zc = prm->zchunk;
+    if (c.zc <= 0) c.zc = auto_zc(nx, ny, nz, c.tx, c.ty);
+    c.zc = std::min(c.zc, nz);
+    return c;
+}
+
+// ------------------------------------------------------------------ engine
+
+struct Inst {
+    // problem
+    const uint8_t *mask = nullptr;
+    int nx = 0, ny = 0, nz = 0, axis = 0;
+    int64_t N = 0;
+    double dx = 1.0, mu = 1.0;
+    void *user[4] = {nullptr, nullptr, nullptr, nullptr};
+    pm_history *hist = nullptr;
+    // derived
+    uint32_t *codes = nullptr;
+    int64_t nflow = 0, nsolid = 0;
+    // state
+    bool dc = false;
+    Prec prec = kF64;
+    void *set[2][4] = {};
+    void *internal = nullptr;
+    int64_t local_n = 0, sweeps = 0;
+    double rmin = INFINITY, qprev = -1.0;
+    int stall = 0;
+    double r_last = INFINITY;
+    bool active = false, needs_start = false;
+    pm_status status = PM_OK;
+    double kcol[3] = {0, 0, 0};
+    TileCfg tile;
+    int64_t nblocks = 0, partial_rows = 0;
+    double *partials = nullptr;
+};
+
+int64_t blocks_of(const Inst &in)
+{
+    return (int64_t)((in.nx + in.tile.tx - 1) / in.tile.tx) * ((in.ny + in.tile.ty - 1) / in.tile.ty) *
+           ((in.nz + in.tile.zc - 1) / in.tile.zc);
+}
+
+size_t elem(Prec p) { return p == kF64 ? sizeof(double) : sizeof(float); }
+
+struct Engine {
+    pm_ctx *ctx;
+    hipStream_t stream;
+    const pm_params *prm;
+    std::vector<Inst> &inst;
+    Scratch scratch;
+    // device tables
+    InstDev *d_tab = nullptr;
+    size_t d_tab_cap = 0;
+    PartialRef *d_refs = nullptr;
+    double *d_sums = nullptr;
+    std::vector<InstDev> h_tab;
+    std::vector<PartialRef> h_refs;
+
+    Engine(pm_ctx *c, hipStream_t s, const pm_params *p, std::vector<Inst> &i)
+        : ctx(c), stream(s), prm(p), inst(i), scratch(c) {}
+
+    pm_status prepare()
+    {
+        // stencil codes and counts, once per distinct mask
+        std::map<const void *, size_t> first_of;
+        for (size_t i = 0; i < inst.size(); ++i) {
+            Inst &in = inst[i];
+            auto it = first_of.find(in.mask);
+            if (it != first_of.end()) {
+                const Inst &o = inst[it->second];
+                if (o.nx == in.nx && o.ny == in.ny && o.nz == in.nz) {
+                    in.codes = o.codes;
+                    in.nsolid = o.nsolid;
+                    continue;
+                }
+            } else {
+                first_of[in.mask] = i;
+            }
+            void *p = nullptr;
+            PM_TRY(scratch.get((size_t)in.N * sizeof(uint32_t), &p));
+            in.codes = (uint32_t *)p;
+            PM_HIP(launch_face_codes(in.mask, in.nx, in.ny, in.nz, in.codes, stream));
+        }
+        void *dcount = nullptr;
+        PM_TRY(scratch.get(4 * sizeof(unsigned long long) * inst.size(), &dcount));
+        unsigned long long *cnt = (unsigned long long *)dcount;
+        for (size_t i = 0; i < inst.size(); ++i)
+            PM_HIP(launch_counts(inst[i].mask, inst[i].codes, inst[i].N, cnt + 4 * i, stream));
+        std::vector<unsigned long long> hc(4 * inst.size());
+        PM_HIP(hipMemcpyAsync(hc.data(), cnt, hc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                              stream));
+        PM_HIP(hipStreamSynchronize(stream));
+        for (size_t i = 0; i < inst.size(); ++i) {
+            Inst &in = inst[i];
+            in.nsolid = (int64_t)hc[4 * i];
+            in.nflow = (int64_t)hc[4 * i + 1 + in.axis];
+            in.active = true;
+            if (in.nsolid == 0 || in.nflow == 0) {
+                in.status = PM_ERR_NO_FLOW;
+                in.active = false;
+            }
+        }
+        // fields and partials
+        int64_t total_blocks = 0;
+        for (Inst &in : inst) {
+            if (!in.active) continue;
+            in.dc = prm->precision == PM_FP32_DC;
+            in.prec = prm->precision == PM_FP64 ? kF64 : kF32;
+            const Prec user_prec = prm->precision == PM_FP32 ? kF32 : kF64;
+            const size_t ue = elem(user_prec);
+            if (!in.user[0]) {
+                void *p = nullptr;
+                PM_TRY(scratch.get(4 * (size_t)in.N * ue, &p));
+                for (int f = 0; f < 4; ++f) in.user[f] = (char *)p + f * (size_t)in.N * ue;
+            }
+            // one internal block of 4 N user-precision values: the second set
+            // (FP64/FP32) or, for FP32_DC, both FP32 sets of the first phase
+            PM_TRY(scratch.get(4 * (size_t)in.N * ue, &in.internal));
+            if (in.dc) {
+                for (int s = 0; s < 2; ++s)
+                    for (int f = 0; f < 4; ++f)
+                        in.set[s][f] = (char *)in.internal + (size_t)(4 * s + f) * in.N * sizeof(float);
+            } else {
+                for (int f = 0; f < 4; ++f) {
+                    in.set[0][f] = in.user[f];
+                    in.set[1][f] = (char *)in.internal + (size_t)f * in.N * ue;
+                }
+            }
+            in.tile = pick_tiles(ctx, prm, in.nx, in.ny, in.nz, in.prec);
+            in.nblocks = blocks_of(in);
+            if (in.dc) {  // room for the FP64 phase's decomposition too
+                Inst tmp = in;
+                tmp.tile = pick_tiles(ctx, prm, in.nx, in.ny, in.nz, kF64);
+                in.partial_rows = std::max(in.nblocks, blocks_of(tmp));
+            } else {
+                in.partial_rows = in.nblocks;
+            }
+            total_blocks += in.partial_rows;
+        }
+        if (total_blocks > 0) {
+            void *p = nullptr;
+            PM_TRY(scratch.get((size_t)total_blocks * kNumSums * sizeof(double), &p));
+            double *base = (double *)p;
+            for (Inst &in : inst)
+                if (in.active) {
+                    in.partials = base;
+                    base += in.partial_rows * kNumSums;
+                }
+        }
+        void *p = nullptr;
+        PM_TRY(scratch.get(inst.size() * sizeof(InstDev), &p));
+        d_tab = (InstDev *)p;
+        PM_TRY(scratch.get(inst.size() * sizeof(PartialRef), &p));
+        d_refs = (PartialRef *)p;
+        PM_TRY(scratch.get(inst.size() * kNumSums * sizeof(double), &p));
+        d_sums = (double *)p;
+        PM_TRY(ensure_host_sums(ctx, inst.size() * kNumSums));
+        return PM_OK;
+    }
+
+    pm_status init_state()
+    {
+        for (Inst &in : inst) {
+            if (!in.active) continue;
+            const size_t ue = prm->precision == PM_FP32 ? sizeof(float) : sizeof(double);
+            if (!prm->warm_start) {
+                for (int f = 0; f < 4; ++f) PM_HIP(hipMemsetAsync(in.user[f], 0, (size_t)in.N * ue, stream));
+            } else {
+                PM_HIP(launch_zero_solid(prm->precision == PM_FP32 ? kF32 : kF64, in.codes, in.N, in.user[0],
+                                         in.user[1], in.user[2], stream));
+            }
+            if (in.dc) {
+                for (int f = 0; f < 4; ++f)
+                    PM_HIP(launch_f64_to_f32((const double *)in.user[f], (float *)in.set[0][f], in.N, stream));
+            }
+            in.needs_start = true;
+            in.local_n = 0;
+        }
+        return PM_OK;
+    }
+
+    InstDev dev_of(const Inst &in, int64_t blk_begin, bool skip) const
+    {
+        InstDev d;
+        d.nx = in.nx;
+        d.ny = in.ny;
+        d.nz = in.nz;
+        d.axis = in.axis;
+        d.tiles_x = (in.nx + in.tile.tx - 1) / in.tile.tx;
+        d.tiles_y = (in.ny + in.tile.ty - 1) / in.tile.ty;
+        d.tiles_z = (in.nz + in.tile.zc - 1) / in.tile.zc;
+        d.zc = in.tile.zc;
+        d.blk_begin = blk_begin;
+        d.nblocks = in.nblocks;
+        d.codes = in.codes;
+        for (int s = 0; s < 2; ++s)
+            for (int f = 0; f < 3; ++f) d.vel[s][f] = in.set[s][f];
+        d.pres[0] = in.set[0][3];
+        d.pres[1] = in.set[1][3];
+        d.partials = in.partials;
+        d.nu = 1.0 / prm->re;
+        d.dt = prm->dt;
+        d.c2dt = prm->c2 * prm->dt;
+        d.drive = prm->drive;
+        d.par_off = skip ? 0 : (int)((in.local_n + 1) & 1);
+        d.skip = skip ? 1 : 0;
+        return d;
+    }
+
+    // Launch `steps` fused sweeps for the selected instances (reduce on the
+    // last) and bring their sums to ctx->h_sums in selection order.
+    pm_status run_block(const std::vector<int> &sel, int steps, bool skip)
+    {
+        // one sub-table per (precision, tile) group, contiguous in d_tab
+        h_tab.clear();
+        h_refs.clear();
+        struct Group {
+            Prec prec;
+            int tx, ty;
+            int first, count;
+            int64_t blocks;
+        };
+        std::vector<Group> groups;
+        std::vector<int> order;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int i : sel) {
+                const Inst &in = inst[i];
+                if ((pass == 0) != (in.prec == kF64)) continue;
+                if (groups.empty() || groups.back().prec != in.prec || groups.back().tx != in.tile.tx ||
+                    groups.back().ty != in.tile.ty)
+                    groups.push_back({in.prec, in.tile.tx, in.tile.ty, (int)h_tab.size(), 0, 0});
+                Group &g = groups.back();
+                h_tab.push_back(dev_of(in, g.blocks, skip));
+                g.blocks += in.nblocks;
+                g.count++;
+                order.push_back(i);
+            }
+        for (int i : order) h_refs.push_back({inst[i].partials, inst[i].nblocks});
+        PM_HIP(hipMemcpyAsync(d_tab, h_tab.data(), h_tab.size() * sizeof(InstDev), hipMemcpyHostToDevice, stream));
+        PM_HIP(hipMemcpyAsync(d_refs, h_refs.data(), h_refs.size() * sizeof(PartialRef), hipMemcpyHostToDevice,
+                              stream));
+        for (int j = 0; j < steps; ++j)
+            for (const Group &g : groups)
+                PM_HIP(launch_fused(g.prec, g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1,
+                                    j == steps - 1 ? 1 : 0, stream));
+        PM_HIP(launch_reduce_partials(d_refs, (int)order.size(), d_sums, stream));
+        PM_HIP(hipMemcpyAsync(ctx->h_sums, d_sums, order.size() * kNumSums * sizeof(double),
+                              hipMemcpyDeviceToHost, stream));
+        PM_HIP(hipStreamSynchronize(stream));
+        // h_sums rows follow `order`; remap to `sel` positions
+        sums_of.assign(inst.size(), nullptr);
+        for (size_t r = 0; r < order.size(); ++r) sums_of[order[r]] = ctx->h_sums + r * kNumSums;
+        return PM_OK;
+    }
+    std::vector<const double *> sums_of;
+
+    void record(Inst &in, const double *s, double r, double eps)
+    {
+        for (int k = 0; k < 3; ++k)
+            in.kcol[k] = s[2 + k] / ((double)in.N * prm->re * prm->drive) * in.dx * in.dx;
+        pm_history *h = in.hist;
+        if (h && h->n < h->cap) {
+            const int64_t j = h->n++;
+            if (h->sweep) h->sweep[j] = in.sweeps;
+            if (h->resid) h->resid[j] = r;
+            if (h->eps_q) h->eps_q[j] = eps;
+            if (h->q)
+                for (int k = 0; k < 3; ++k) h->q[3 * j + k] = s[2 + k] / (double)in.N;
+        }
+    }
+
+    // Copy the state of the last check into the user fields.
+    pm_status finalize(Inst &in)
+    {
+        const int vs = (int)(in.local_n & 1), ps_ = (int)((in.local_n + 1) & 1);
+        const size_t e = elem(in.prec);
+        // in the final phase set 0 is the user set (FP64, FP32) -- for FP32_DC the
+        // FP32 phase never finalises with status OK, but may with an error status
+        if (in.dc && in.prec == kF32) {
+            for (int f = 0; f < 3; ++f)
+                PM_HIP(launch_f32_to_f64((const float *)in.set[vs][f], (double *)in.user[f], in.N, stream));
+            PM_HIP(launch_f32_to_f64((const float *)in.set[ps_][3], (double *)in.user[3], in.N, stream));
+        } else {
+            if (vs != 0)
+                for (int f = 0; f < 3; ++f)
+                    PM_HIP(hipMemcpyAsync(in.user[f], in.set[vs][f], (size_t)in.N * e, hipMemcpyDeviceToDevice,
+                                          stream));
+            if (ps_ != 0)
+                PM_HIP(hipMemcpyAsync(in.user[3], in.set[ps_][3], (size_t)in.N * e, hipMemcpyDeviceToDevice,
+                                      stream));
+        }
+        in.active = false;
+        return PM_OK;
+    }
+
+    // FP32 phase -> FP64 phase from the promoted state.
+    pm_status promote(Inst &in)
+    {
+        const int vs = (int)(in.local_n & 1), ps_ = (int)((in.local_n + 1) & 1);
+        for (int f = 0; f < 3; ++f)
+            PM_HIP(launch_f32_to_f64((const float *)in.set[vs][f], (double *)in.user[f], in.N, stream));
+        PM_HIP(launch_f32_to_f64((const float *)in.set[ps_][3], (double *)in.user[3], in.N, stream));
+        in.prec = kF64;
+        for (int f = 0; f < 4; ++f) {
+            in.set[0][f] = in.user[f];
+            in.set[1][f] = (char *)in.internal + (size_t)f * in.N * sizeof(double);
+        }
+        in.tile = pick_tiles(ctx, prm, in.nx, in.ny, in.nz, kF64);
+        const int64_t nb = blocks_of(in);
+        if (nb > in.partial_rows) return fail(ctx, PM_ERR_ARG, "internal: block count grew on promotion");
+        in.nblocks = nb;
+        in.local_n = 0;
+        in.needs_start = true;
+        in.rmin = INFINITY;
+        in.stall = 0;
+        return PM_OK;
+    }
+
+    // Convergence bookkeeping after a check of instance `in` with sums s.
+    pm_status check(Inst &in, const double *s)
+    {
+        const double r = std::sqrt(s[0] + s[1]) / (prm->drive * std::sqrt((double)in.nflow));
+        const double qn = std::sqrt(s[2] * s[2] + s[3] * s[3] + s[4] * s[4]) / (double)in.N;
+        const double eps = (in.qprev >= 0.0 && qn > 0.0) ? std::fabs(qn - in.qprev) / qn : INFINITY;
+        in.qprev = qn;
+        record(in, s, r, eps);
+        in.r_last = r;
+        if (!std::isfinite(r) || r > 1e3 * in.rmin) {
+            in.status = PM_DIVERGED;
+            return finalize(in);
+        }
+        if (r < in.rmin) {
+            in.rmin = r;
+            in.stall = 0;
+        } else {
+            in.stall++;
+        }
+        const bool met = prm->stop_rule == 0 ? r < prm->tol : eps < prm->tol;
+        const bool fp32_phase = in.prec == kF32;
+        if (in.dc && fp32_phase) {
+            // hand over to FP64 once the FP32 iterate reaches the switch level,
+            // meets tol, or stops improving (its rounding floor)
+            const double sw = std::max(prm->tol, dc_switch());
+            if (met || r < sw || in.stall >= 5) return promote(in);
+        } else if (met) {
+            in.status = PM_OK;
+            return finalize(in);
+        }
+        if (!in.dc && fp32_phase && in.stall >= 8) {
+            in.status = PM_NOT_CONVERGED;  // FP32 rounding floor above tol
+            return finalize(in);
+        }
+        if (in.sweeps >= prm->max_sweeps) {
+            in.status = PM_NOT_CONVERGED;
+            return finalize(in);
+        }
+        return PM_OK;
+    }
+
+    double dc_switch() const { return 1e-6; }
+
+    pm_status run()
+    {
+        PM_TRY(prepare());
+        PM_TRY(init_state());
+        for (;;) {
+            std::vector<int> starters, actives;
+            for (int i = 0; i < (int)inst.size(); ++i)
+                if (inst[i].active && inst[i].needs_start) starters.push_back(i);
+            if (!starters.empty()) {
+                PM_TRY(run_block(starters, 1, true));
+                for (int i : starters) {
+                    inst[i].needs_start = false;
+                    PM_TRY(check(inst[i], sums_of[i]));
+                }
+                continue;  // promotions inside the check restart their pipeline
+            }
+            int64_t remaining = INT64_MAX;
+            for (int i = 0; i < (int)inst.size(); ++i)
+                if (inst[i].active) {
+                    actives.push_back(i);
+                    remaining = std::min(remaining, prm->max_sweeps - inst[i].sweeps);
+                }
+            if (actives.empty()) break;
+            // a check at every multiple of check_every and at max_sweeps
+            int64_t to_next = prm->check_every - (inst[actives[0]].sweeps % prm->check_every);
+            const int steps = (int)std::max<int64_t>(1, std::min(to_next, remaining));
+            PM_TRY(run_block(actives, steps, false));
+            for (int i : actives) {
+                inst[i].local_n += steps;
+                inst[i].sweeps += steps;
+                PM_TRY(check(inst[i], sums_of[i]));
+            }
+        }
+        PM_HIP(hipStreamSynchronize(stream));
+        return PM_OK;
+    }
+};
+
+int severity(pm_status s)
+{
+    switch (s) {
+    case PM_OK: return 0;
+    case PM_NOT_CONVERGED: return 1;
+    case PM_ERR_NO_FLOW: return 2;
+    case PM_DIVERGED: return 3;
+    default: return 4;
+    }
+}
+
+pm_status check_instance_args(pm_ctx *ctx, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz, int axis,
+                              double dx, double mu, void *const f[4], bool fields_required, size_t align)
+{
+    if (!mask) return fail(ctx, PM_ERR_ARG, "mask is NULL");
+    PM_TRY(check_dims(ctx, nx, ny, nz));
+    if (axis < 0 || axis > 2) return fail(ctx, PM_ERR_ARG, "axis must be 0, 1 or 2 (got %d)", axis);
+    if (!(dx > 0) || !std::isfinite(dx)) return fail(ctx, PM_ERR_ARG, "voxel_size must be positive");
+    if (!(mu > 0) || !std::isfinite(mu)) return fail(ctx, PM_ERR_ARG, "mu must be positive");
+    int nnull = 0;
+    for (int i = 0; i < 4; ++i) {
+        if (!f[i]) ++nnull;
+        else if (!aligned(f[i], align)) return fail(ctx, PM_ERR_ARG, "field %d is misaligned", i);
+    }
+    if (fields_required && nnull) return fail(ctx, PM_ERR_ARG, "field pointers must not be NULL");
+    if (nnull != 0 && nnull != 4) return fail(ctx, PM_ERR_ARG, "give all four field pointers or none");
+    return PM_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+void pm_params_default(pm_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->re = 0.01;
+    p->c2 = 1.5e6;
+    p->dt = 1.0 / 4096.0;
+    p->tol = 1e-8;
+    p->drive = 1.0;
+    p->max_sweeps = 10000000;
+    p->check_every = 100;
+    p->precision = PM_FP64;
+    p->stop_rule = 0;
+    p->warm_start = 0;
+    p->kernel = PM_KERNEL_AUTO;
+}
+
+const char *pm_status_string(pm_status s)
+{
+    switch (s) {
+    case PM_OK: return "PM_OK";
+    case PM_ERR_ARG: return "PM_ERR_ARG";
+    case PM_ERR_OOM: return "PM_ERR_OOM";
+    case PM_ERR_DEVICE: return "PM_ERR_DEVICE";
+    case PM_NOT_CONVERGED: return "PM_NOT_CONVERGED";
+    case PM_DIVERGED: return "PM_DIVERGED";
+    case PM_ERR_NO_FLOW: return "PM_ERR_NO_FLOW";
+    }
+    return "PM_UNKNOWN";
+}
+
+pm_status pm_create(int hip_device, size_t mem_cap_bytes, pm_ctx **out)
+{
+    if (!out) return PM_ERR_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) {
+        (void)hipGetLastError();
+        return hip_device < 0 ? PM_ERR_ARG : PM_ERR_DEVICE;
+    }
+    pm_ctx *ctx = new (std::nothrow) pm_ctx();
+    if (!ctx) return PM_ERR_OOM;
+    ctx->dev = hip_device;
+    ctx->cap = mem_cap_bytes;
+    if (hipSetDevice(hip_device) != hipSuccess) {
+        delete ctx;
+        return PM_ERR_DEVICE;
+    }
+    *out = ctx;
+    return PM_OK;
+}
+
+void pm_destroy(pm_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->dev);
+    for (auto &kv : ctx->allocs) (void)hipFree(kv.first);
+    if (ctx->h_sums) (void)hipHostFree(ctx->h_sums);
+    delete ctx;
+}
+
+const char *pm_last_error(const pm_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+size_t pm_mem_used(const pm_ctx *ctx) { return ctx ? ctx->used : 0; }
+
+pm_status pm_preprocess(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz,
+                        uint32_t *bits)
+{
+    if (!ctx) return PM_ERR_ARG;
+    ctx->err.clear();
+    if (!mask || !bits) return fail(ctx, PM_ERR_ARG, "mask and bits must not be NULL");
+    PM_TRY(check_dims(ctx, nx, ny, nz));
+    if (!aligned(bits, 4)) return fail(ctx, PM_ERR_ARG, "bits is misaligned");
+    PM_TRY(set_device(ctx));
+    PM_HIP(launch_face_bits(mask, (int)nx, (int)ny, (int)nz, bits, (hipStream_t)stream));
+    return PM_OK;
+}
+
+pm_status pm_face_codes(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz,
+                        uint32_t *codes)
+{
+    if (!ctx) return PM_ERR_ARG;
+    ctx->err.clear();
+    if (!mask || !codes) return fail(ctx, PM_ERR_ARG, "mask and codes must not be NULL");
+    PM_TRY(check_dims(ctx, nx, ny, nz));
+    if (!aligned(codes, 4)) return fail(ctx, PM_ERR_ARG, "codes is misaligned");
+    PM_TRY(set_device(ctx));
+    PM_HIP(launch_face_codes(mask, (int)nx, (int)ny, (int)nz, codes, (hipStream_t)stream));
+    return PM_OK;
+}
+
+pm_status pm_iterate(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz, int axis,
+                     const pm_params *params, void *u, void *v, void *w, void *p, int64_t count)
+{
+    if (!ctx) return PM_ERR_ARG;
+    ctx->err.clear();
+    PM_TRY(check_params(ctx, params));
+    if (params->precision == PM_FP32_DC) return fail(ctx, PM_ERR_ARG, "pm_iterate takes PM_FP64 or PM_FP32");
+    const Prec prec = params->precision == PM_FP64 ? kF64 : kF32;
+    void *f[4] = {u, v, w, p};
+    PM_TRY(check_instance_args(ctx, mask, nx, ny, nz, axis, 1.0, 1.0, f, true, elem(prec)));
+    if (count < 0) return fail(ctx, PM_ERR_ARG, "count must be >= 0");
+    PM_TRY(set_device(ctx));
+    hipStream_t s = (hipStream_t)stream;
+    if (count == 0) return PM_OK;
+    const int64_t N = nx * ny * nz;
+    Scratch scratch(ctx);
+    void *codes = nullptr, *second = nullptr;
+    PM_TRY(scratch.get((size_t)N * 4, &codes));
+    PM_TRY(scratch.get(4 * (size_t)N * elem(prec), &second));
+    PM_HIP(launch_face_codes(mask, (int)nx, (int)ny, (int)nz, (uint32_t *)codes, s));
+    PM_HIP(launch_zero_solid(prec, (const uint32_t *)codes, N, u, v, w, s));
+    void *set[2][4];
+    for (int k = 0; k < 4; ++k) {
+        set[0][k] = f[k];
+        set[1][k] = (char *)second + (size_t)k * N * elem(prec);
+    }
+    const double nu = 1.0 / params->re, c2dt = params->c2 * params->dt;
+    if (params->kernel == PM_KERNEL_SIMPLE) {
+        for (int64_t n = 0; n < count; ++n) {
+            const int a = (int)(n & 1);
+            PM_HIP(launch_simple_sweep(prec, (int)nx, (int)ny, (int)nz, axis, (const uint32_t *)codes, set[a],
+                                       set[a ^ 1], nu, params->dt, c2dt, params->drive, s));
+        }
+        if (count & 1)
+            for (int k = 0; k < 4; ++k)
+                PM_HIP(hipMemcpyAsync(f[k], set[1][k], (size_t)N * elem(prec), hipMemcpyDeviceToDevice, s));
+        return PM_OK;
+    }
+    // fused: launches K_0 (pressure passthrough) .. K_count; state count is
+    // v^count (set count&1) and p^count (set (count+1)&1)
+    Inst in;
+    in.nx = (int)nx;
+    in.ny = (int)ny;
+    in.nz = (int)nz;
+    in.axis = axis;
+    in.N = N;
+    in.codes = (uint32_t *)codes;
+    in.prec = prec;
+    for (int k = 0; k < 4; ++k) {
+        in.set[0][k] = set[0][k];
+        in.set[1][k] = set[1][k];
+    }
+    in.tile = pick_tiles(ctx, params, in.nx, in.ny, in.nz, prec);
+    in.nblocks = blocks_of(in);
+    void *part = nullptr, *tab = nullptr;
+    PM_TRY(scratch.get((size_t)in.nblocks * kNumSums * sizeof(double), &part));
+    PM_TRY(scratch.get(2 * sizeof(InstDev), &tab));
+    in.partials = (double *)part;
+    std::vector<Inst> one(1, in);
+    Engine eng(ctx, s, params, one);
+    InstDev d[2] = {eng.dev_of(in, 0, true), eng.dev_of(in, 0, false)};
+    d[1].par_off = 1;  // sweeps K_1.. read set (n & 1) with launch parity j & 1 for n = j + 1
+    PM_HIP(hipMemcpyAsync(tab, d, sizeof d, hipMemcpyHostToDevice, s));
+    InstDev *dt = (InstDev *)tab;
+    PM_HIP(launch_fused(prec, in.tile.tx, in.tile.ty, dt, 1, in.nblocks, 0, 0, s));
+    for (int64_t n = 1; n <= count; ++n)
+        PM_HIP(launch_fused(prec, in.tile.tx, in.tile.ty, dt + 1, 1, in.nblocks, (int)((n - 1) & 1), 0, s));
+    const int vs = (int)(count & 1), ps_ = (int)((count + 1) & 1);
+    if (vs)
+        for (int k = 0; k < 3; ++k)
+            PM_HIP(hipMemcpyAsync(f[k], set[1][k], (size_t)N * elem(prec), hipMemcpyDeviceToDevice, s));
+    if (ps_) PM_HIP(hipMemcpyAsync(f[3], set[1][3], (size_t)N * elem(prec), hipMemcpyDeviceToDevice, s));
+    // the scratch buffers are freed on return: finish the work that reads them
+    PM_HIP(hipStreamSynchronize(s));
+    return PM_OK;
+}
+
+pm_status pm_residual(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz, int axis,
+                      const pm_params *params, const void *u, const void *v, const void *w, const void *p,
+                      double out[5])
+{
+    if (!ctx) return PM_ERR_ARG;
+    ctx->err.clear();
+    PM_TRY(check_params(ctx, params));
+    if (params->precision == PM_FP32_DC) return fail(ctx, PM_ERR_ARG, "pm_residual takes PM_FP64 or PM_FP32");
+    if (!out) return fail(ctx, PM_ERR_ARG, "out is NULL");
+    const Prec prec = params->precision == PM_FP64 ? kF64 : kF32;
+    void *f[4] = {(void *)u, (void *)v, (void *)w, (void *)p};
+    PM_TRY(check_instance_args(ctx, mask, nx, ny, nz, axis, 1.0, 1.0, f, true, elem(prec)));
+    PM_TRY(set_device(ctx));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t N = nx * ny * nz;
+    Scratch scratch(ctx);
+    void *codes = nullptr, *part = nullptr, *refs = nullptr, *sums = nullptr;
+    PM_TRY(scratch.get((size_t)N * 4, &codes));
+    PM_TRY(scratch.get((size_t)state_sums_blocks(N) * kNumSums * sizeof(double), &part));
+    PM_TRY(scratch.get(sizeof(PartialRef), &refs));
+    PM_TRY(scratch.get(kNumSums * sizeof(double), &sums));
+    PM_HIP(launch_face_codes(mask, (int)nx, (int)ny, (int)nz, (uint32_t *)codes, s));
+    int64_t nb = 0;
+    PM_HIP(launch_state_sums(prec, (int)nx, (int)ny, (int)nz, axis, (const uint32_t *)codes, f, 1.0 / params->re,
+                             params->drive, (double *)part, &nb, s));
+    PartialRef r{(const double *)part, nb};
+    PM_HIP(hipMemcpyAsync(refs, &r, sizeof r, hipMemcpyHostToDevice, s));
+    PM_HIP(launch_reduce_partials((const PartialRef *)refs, 1, (double *)sums, s));
+    PM_HIP(hipMemcpyAsync(out, sums, kNumSums * sizeof(double), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    return PM_OK;
+}
+
+pm_status pm_solve_batch(pm_ctx *ctx, void *stream, pm_instance *insts, int32_t n, const pm_params *params)
+{
+    if (!ctx) return PM_ERR_ARG;
+    ctx->err.clear();
+    PM_TRY(check_params(ctx, params));
+    if (!insts || n < 1) return fail(ctx, PM_ERR_ARG, "need at least one instance");
+    if (params->kernel == PM_KERNEL_SIMPLE)
+        return fail(ctx, PM_ERR_ARG, "solves use the fused kernel (PM_KERNEL_SIMPLE is for pm_iterate)");
+    const size_t align = params->precision == PM_FP32 ? sizeof(float) : sizeof(double);
+    std::vector<Inst> list((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        pm_instance &pi = insts[i];
+        void *f[4] = {pi.u, pi.v, pi.w, pi.p};
+        pm_status s = check_instance_args(ctx, pi.mask, pi.nx, pi.ny, pi.nz, pi.axis, pi.voxel_size, pi.mu, f,
+                                          false, align);
+        if (s != PM_OK) {
+            ctx->err = "instance " + std::to_string(i) + ": " + ctx->err;
+            return s;
+        }
+        if (params->warm_start && !pi.u)
+            return fail(ctx, PM_ERR_ARG, "instance %d: warm_start needs field pointers", i);
+        Inst &in = list[i];
+        in.mask = pi.mask;
+        in.nx = (int)pi.nx;
+        in.ny = (int)pi.ny;
+        in.nz = (int)pi.nz;
+        in.N = pi.nx * pi.ny * pi.nz;
+        in.axis = pi.axis;
+        in.dx = pi.voxel_size;
+        in.mu = pi.mu;
+        for (int k = 0; k < 4; ++k) in.user[k] = f[k];
+        in.hist = pi.hist;
+        if (in.hist) in.hist->n = 0;
+    }
+    PM_TRY(set_device(ctx));
+    Engine eng(ctx, (hipStream_t)stream, params, list);
+    pm_status rs = eng.run();
+    pm_status worst = PM_OK;
+    for (int i = 0; i < n; ++i) {
+        pm_instance &pi = insts[i];
+        const Inst &in = list[i];
+        pi.status = rs != PM_OK ? rs : in.status;
+        pi.sweeps = in.sweeps;
+        for (int k = 0; k < 3; ++k) pi.k_col[k] = in.kcol[k];
+        if (severity((pm_status)pi.status) > severity(worst)) worst = (pm_status)pi.status;
+    }
+    return rs != PM_OK ? rs : worst;
+}
+
+pm_status pm_solve(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz,
+                   double voxel_size, double mu, int axis, const pm_params *params, void *u, void *v, void *w,
+                   void *p, pm_history *hist, double k_col[3], int64_t *sweeps_done)
+{
+    if (!ctx) return PM_ERR_ARG;
+    ctx->err.clear();
+    if (!k_col) return fail(ctx, PM_ERR_ARG, "k_col is NULL");
+    if (!u || !v || !w || !p) return fail(ctx, PM_ERR_ARG, "field pointers must not be NULL");
+    pm_instance in;
+    std::memset(&in, 0, sizeof in);
+    in.mask = mask;
+    in.nx = nx;
+    in.ny = ny;
+    in.nz = nz;
+    in.voxel_size = voxel_size;
+    in.mu = mu;
+    in.axis = axis;
+    in.u = u;
+    in.v = v;
+    in.w = w;
+    in.p = p;
+    in.hist = hist;
+    pm_status s = pm_solve_batch(ctx, stream, &in, 1, params);
+    for (int k = 0; k < 3; ++k) k_col[k] = in.k_col[k];
+    if (sweeps_done) *sweeps_done = in.sweeps;
+    return s;
+}
+
+pm_status pm_tensor(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz,
+                    double voxel_size, double mu, const pm_params *params, double k[9], double k_sym[9],
+                    pm_history *hist, int64_t sweeps[3])
+{
+    if (!ctx) return PM_ERR_ARG;
+    ctx->err.clear();
+    if (!k || !k_sym) return fail(ctx, PM_ERR_ARG, "k and k_sym must not be NULL");
+    pm_instance in[3];
+    std::memset(in, 0, sizeof in);
+    for (int j = 0; j < 3; ++j) {
+        in[j].mask = mask;
+        in[j].nx = nx;
+        in[j].ny = ny;
+        in[j].nz = nz;
+        in[j].voxel_size = voxel_size;
+        in[j].mu = mu;
+        in[j].axis = j;
+        in[j].hist = hist ? &hist[j] : nullptr;
+    }
+    if (params && params->warm_start) return fail(ctx, PM_ERR_ARG, "pm_tensor keeps its fields internally");
+    pm_status s = pm_solve_batch(ctx, stream, in, 3, params);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) k[i * 3 + j] = in[j].k_col[i];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) k_sym[i * 3 + j] = 0.5 * (k[i * 3 + j] + k[j * 3 + i]);
+    if (sweeps)
+        for (int j = 0; j < 3; ++j) sweeps[j] = in[j].sweeps;
+    return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Host-visible launch interface of the porestokes kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ps {
+
+enum Prec { kF64 = 0, kF32 = 1 };
+
+// One solve instance as seen by the batched fused sweep kernel.  The table of
+// instances lives in device memory; blocks of one launch are assigned to
+// instances by their [blk_begin, blk_begin + nblocks) range.
+struct InstDev {
+    int32_t nx, ny, nz, axis;
+    int32_t tiles_x, tiles_y, tiles_z, zc;
+    int64_t blk_begin, nblocks;
+    const uint32_t *codes;
+    void *vel[2][3];     // velocity sets; sweep n reads set (n & 1), writes the other
+    void *pres[2];       // pressure sets; sweep n reads p^{n-1} from (n & 1), writes p^n
+    double *partials;    // kNumSums doubles per block (written when reducing)
+    double nu, dt, c2dt, drive;
+    int32_t par_off;     // effective parity = launch parity ^ par_off
+    int32_t skip;        // 1: first sweep of a pipeline, pressure passes through
+};
+
+// Reference to one instance's block partials for the final reduction.
+struct PartialRef {
+    const double *partials;
+    int64_t nblocks;
+};
+
+hipError_t launch_face_bits(const uint8_t *mask, int nx, int ny, int nz, uint32_t *bits,
+                            hipStream_t s);
+hipError_t launch_face_codes(const uint8_t *mask, int nx, int ny, int nz, uint32_t *codes,
+                             hipStream_t s);
+// counts (device, 4 x uint64, zeroed by the launcher): solid voxels, fluid x/y/z faces
+hipError_t launch_counts(const uint8_t *mask, const uint32_t *codes, int64_t n,
+                         unsigned long long *counts, hipStream_t s);
+// set faces flagged solid in codes to zero
+hipError_t launch_zero_solid(Prec prec, const uint32_t *codes, int64_t n, void *u, void *v, void *w,
+                             hipStream_t s);
+// elementwise conversions and copies of n values
+hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream_t s);
+
+// Fused sweep over the instances of a device table (all of precision prec).
+hipError_t launch_fused(Prec prec, int tile_x, int tile_y, const InstDev *insts, int ninst,
+                        int64_t nblocks, int parity, int reduce, hipStream_t s);
+bool fused_tile_supported(int tile_x, int tile_y);
+
+// Final deterministic reduction: out[i * kNumSums + j] = sum over blocks of refs[i].
+hipError_t launch_reduce_partials(const PartialRef *refs, int ninst, double *out, hipStream_t s);
+
+// Two-pass reference sweep (velocity, then pressure), one thread per cell.
+hipError_t launch_simple_sweep(Prec prec, int nx, int ny, int nz, int axis, const uint32_t *codes,
+                               const void *const in[4], void *const out[4], double nu, double dt,
+                               double c2dt, double drive, hipStream_t s);
+
+// Residual sums of a state into partials (one row of kNumSums per block);
+// returns the number of blocks used through *nblocks.
+hipError_t launch_state_sums(Prec prec, int nx, int ny, int nz, int axis, const uint32_t *codes,
+                             const void *const st[4], double nu, double drive, double *partials,
+                             int64_t *nblocks, hipStream_t s);
+int64_t state_sums_blocks(int64_t n);
+
+}  // namespace ps

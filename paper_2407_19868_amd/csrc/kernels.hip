@@ -1,0 +1,686 @@
+// porestokes device kernels for gfx950 (MI355X).
+//
+//   face_bits / face_codes  mask -> face flags and per-cell stencil codes
+//                           ("Evaluate neighborhood", Algorithm 1; §4, App. B)
+//   fused sweep             one HBM pass per pseudo-time step (§3, Algorithm 1)
+//   simple sweep            two-pass reference of the same arithmetic
+//   state sums              FP64 residual and flux sums (convergence, Darcy)
+#include "common.h"
+#include "kernels.h"
+
+namespace ps {
+
+// ============================================================== preprocessing
+
+__device__ __forceinline__ int wrap_small(int i, int n)
+{
+    // i in (-3n, 3n): cheap periodic wrap for stencil offsets
+    while (i < 0) i += n;
+    while (i >= n) i -= n;
+    return i;
+}
+
+__device__ __forceinline__ bool face_solid(const uint8_t *__restrict__ mask, int nx, int ny, int nz,
+                                           int k, int x, int y, int z)
+{
+    x = wrap_small(x, nx);
+    y = wrap_small(y, ny);
+    z = wrap_small(z, nz);
+    int bx = x, by = y, bz = z;
+    if (k == 0) bx = wrap_small(x - 1, nx);
+    else if (k == 1) by = wrap_small(y - 1, ny);
+    else bz = wrap_small(z - 1, nz);
+    const int64_t plane = (int64_t)nx * ny;
+    return mask[z * plane + (int64_t)y * nx + x] != 0 || mask[bz * plane + (int64_t)by * nx + bx] != 0;
+}
+
+__global__ void k_face_bits(const uint8_t *__restrict__ mask, int nx, int ny, int nz, int W,
+                            uint32_t *__restrict__ bits)
+{
+    const int64_t nwords = (int64_t)W * ny * nz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * nwords) return;
+    const int k = (int)(t / nwords);
+    int64_t r = t % nwords;
+    const int w = (int)(r % W);
+    r /= W;
+    const int y = (int)(r % ny);
+    const int z = (int)(r / ny);
+    uint32_t word = 0;
+    for (int b = 0; b < 32; ++b) {
+        const int x = w * 32 + b;
+        if (x < nx && face_solid(mask, nx, ny, nz, k, x, y, z)) word |= 1u << b;
+    }
+    bits[t] = word;
+}
+
+// 3-bit stencil code from the solid flags at offsets -2, -1, +1, +2.
+__device__ __forceinline__ uint32_t make_code(bool sm2, bool sm1, bool sp1, bool sp2)
+{
+    const bool far = (sm1 && !sp1) ? sp2 : ((sp1 && !sm1) ? sm2 : false);
+    return (uint32_t)sm1 | ((uint32_t)sp1 << 1) | ((uint32_t)far << 2);
+}
+
+__global__ void k_face_codes(const uint8_t *__restrict__ mask, int nx, int ny, int nz,
+                             uint32_t *__restrict__ codes)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int x = (int)(t % nx);
+    const int y = (int)((t / nx) % ny);
+    const int z = (int)(t / ((int64_t)nx * ny));
+    uint32_t word = 0;
+    for (int k = 0; k < 3; ++k) {
+        // perpendicular axes in order: u -> (y, z), v -> (x, z), w -> (x, y)
+        const int i1 = (k == 0) ? 1 : 0;
+        const int i2 = (k == 2) ? 1 : 2;
+        uint32_t c = 0;
+        for (int pi = 0; pi < 2; ++pi) {
+            const int i = pi == 0 ? i1 : i2;
+            bool s[4];
+            const int offs[4] = {-2, -1, 1, 2};
+            for (int j = 0; j < 4; ++j) {
+                int q[3] = {x, y, z};
+                q[i] += offs[j];
+                s[j] = face_solid(mask, nx, ny, nz, k, q[0], q[1], q[2]);
+            }
+            c |= make_code(s[0], s[1], s[2], s[3]) << (3 * pi);
+        }
+        if (face_solid(mask, nx, ny, nz, k, x, y, z)) c |= kSolidBit;
+        word |= c << (kCodeBits * k);
+    }
+    codes[t] = word;
+}
+
+__global__ void k_counts(const uint8_t *__restrict__ mask, const uint32_t *__restrict__ codes, int64_t n,
+                         unsigned long long *__restrict__ counts)
+{
+    __shared__ unsigned long long sc[4];
+    if (threadIdx.x < 4) sc[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned long long c[4] = {0, 0, 0, 0};
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        c[0] += mask[t] != 0;
+        const uint32_t w = codes[t];
+        for (int k = 0; k < 3; ++k) c[1 + k] += ((w >> (kCodeBits * k)) & kSolidBit) == 0;
+    }
+    for (int i = 0; i < 4; ++i) atomicAdd(&sc[i], c[i]);
+    __syncthreads();
+    if (threadIdx.x < 4) atomicAdd(&counts[threadIdx.x], sc[threadIdx.x]);
+}
+
+template <typename T>
+__global__ void k_zero_solid(const uint32_t *__restrict__ codes, int64_t n, T *__restrict__ u,
+                             T *__restrict__ v, T *__restrict__ w)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const uint32_t c = codes[t];
+    if (c & kSolidBit) u[t] = T(0);
+    if ((c >> kCodeBits) & kSolidBit) v[t] = T(0);
+    if ((c >> (2 * kCodeBits)) & kSolidBit) w[t] = T(0);
+}
+
+template <typename S, typename D>
+__global__ void k_convert(const S *__restrict__ src, D *__restrict__ dst, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) dst[t] = (D)src[t];
+}
+
+static inline unsigned grid1d(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_face_bits(const uint8_t *mask, int nx, int ny, int nz, uint32_t *bits, hipStream_t s)
+{
+    const int W = (nx + 31) / 32;
+    const int64_t total = 3LL * W * ny * nz;
+    hipLaunchKernelGGL(k_face_bits, dim3(grid1d(total, 256)), dim3(256), 0, s, mask, nx, ny, nz, W, bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_face_codes(const uint8_t *mask, int nx, int ny, int nz, uint32_t *codes, hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    hipLaunchKernelGGL(k_face_codes, dim3(grid1d(n, 256)), dim3(256), 0, s, mask, nx, ny, nz, codes);
+    return hipGetLastError();
+}
+
+hipError_t launch_counts(const uint8_t *mask, const uint32_t *codes, int64_t n, unsigned long long *counts,
+                         hipStream_t s)
+{
+    hipError_t e = hipMemsetAsync(counts, 0, 4 * sizeof(unsigned long long), s);
+    if (e != hipSuccess) return e;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_counts, dim3((unsigned)blocks), dim3(256), 0, s, mask, codes, n, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_solid(Prec prec, const uint32_t *codes, int64_t n, void *u, void *v, void *w,
+                             hipStream_t s)
+{
+    if (prec == kF64)
+        hipLaunchKernelGGL(k_zero_solid<double>, dim3(grid1d(n, 256)), dim3(256), 0, s, codes, n,
+                           (double *)u, (double *)v, (double *)w);
+    else
+        hipLaunchKernelGGL(k_zero_solid<float>, dim3(grid1d(n, 256)), dim3(256), 0, s, codes, n,
+                           (float *)u, (float *)v, (float *)w);
+    return hipGetLastError();
+}
+
+hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(grid1d(n, 256)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(grid1d(n, 256)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+// ============================================================== fused sweep
+//
+// One launch advances every instance of the table by one sweep, fusing the
+// pressure update of sweep n with the velocity update of sweep n+1:
+//
+//   in:  v^n (velocity set n&1), p^{n-1} (pressure set n&1)
+//   p^n     = p^{n-1} - c2 dt div(v^n)                    (skip: p^n = p^{n-1})
+//   v^{n+1} = v^n + dt F(v^n, p^n) on fluid faces, 0 on solid faces
+//   out: p^n, v^{n+1} (the other sets)
+//
+// This reads and writes each of the four fields once per sweep (the
+// velocity-then-pressure order of Algorithm 1 regrouped), and the residual of
+// the state (v^n, p^n) -- F(v^n, p^n) and div v^n -- falls out of the same pass.
+//
+// Work decomposition: a workgroup owns a TX x TY column tile of the x-y plane
+// and a chunk of zc planes, streamed bottom to top.  Per plane the velocity
+// fields are staged in LDS with a 2-cell halo (the App. B stencils reach two
+// faces across the flow); the planes above and below each thread's own column
+// stay in a register window (5 planes for u and v, 3 for w).  The pressure of
+// the plane is computed for the tile plus a one-cell halo at -x and -y (the
+// pressure gradient of a face reads the cell behind it) and kept in LDS.
+
+template <typename T, int TX, int TY>
+struct FusedShared {
+    static constexpr int PX = TX + 4, PY = TY + 4;
+    T u[PY * PX];
+    T v[PY * PX];
+    T w[PY * PX];
+    T p[(TY + 1) * (TX + 1)];
+    Coef<T> tab[8];
+    double red[kNumSums * (TX * TY / 64)];
+};
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY)
+k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
+{
+    constexpr int NT = TX * TY;
+    constexpr int PX = TX + 4, PY = TY + 4;
+    constexpr int NHALO = PX * PY - NT;
+    constexpr int NHP = TX + TY + 1;
+    static_assert(NHALO <= 2 * NT, "halo too large for two loads per thread");
+    static_assert(NHP <= NT, "pressure halo larger than the block");
+    __shared__ FusedShared<T, TX, TY> sh;
+
+    // ---- instance of this block (ranges are sorted by blk_begin)
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (insts[mid].blk_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const InstDev &I = insts[lo];
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
+    const int64_t lb = b - I.blk_begin;
+    const int bx = (int)(lb % I.tiles_x);
+    const int64_t rr = lb / I.tiles_x;
+    const int by = (int)(rr % I.tiles_y);
+    const int bz = (int)(rr / I.tiles_y);
+    const int x0 = bx * TX, y0 = by * TY;
+    const int z0 = bz * I.zc;
+    const int z1 = min(z0 + I.zc, nz);
+    const int64_t plane = (int64_t)nx * ny;
+    const int eff = parity ^ I.par_off;
+    const T *__restrict__ Uin = (const T *)I.vel[eff][0];
+    const T *__restrict__ Vin = (const T *)I.vel[eff][1];
+    const T *__restrict__ Win = (const T *)I.vel[eff][2];
+    const T *__restrict__ Pin = (const T *)I.pres[eff];
+    T *__restrict__ Uout = (T *)I.vel[eff ^ 1][0];
+    T *__restrict__ Vout = (T *)I.vel[eff ^ 1][1];
+    T *__restrict__ Wout = (T *)I.vel[eff ^ 1][2];
+    T *__restrict__ Pout = (T *)I.pres[eff ^ 1];
+    const uint32_t *__restrict__ codes = I.codes;
+    const T nu = (T)I.nu, dt = (T)I.dt, c2dt = (T)I.c2dt;
+    const T gu = I.axis == 0 ? (T)I.drive : T(0);
+    const T gv = I.axis == 1 ? (T)I.drive : T(0);
+    const T gw = I.axis == 2 ? (T)I.drive : T(0);
+    const bool skip = I.skip != 0;
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    if (tid < 8) sh.tab[tid] = coef_of_code<T>(tid);
+
+    // ---- own column (inactive threads hold the wrapped column: LDS stays periodic)
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool active = gx < nx && gy < ny;
+    const int own = wrap_int(gy, ny) * nx + wrap_int(gx, nx);
+    const int cl = (ty + 2) * PX + (tx + 2);  // own position in the padded plane
+
+    // ---- halo positions of the padded plane (up to two per thread)
+    int hoff[2], hlds[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int h = tid + j * NT;
+        hoff[j] = -1;
+        hlds[j] = 0;
+        if (h < NHALO) {
+            int px, py;
+            if (h < 2 * PX) {
+                py = h / PX;
+                px = h % PX;
+            } else if (h < 4 * PX) {
+                const int hh = h - 2 * PX;
+                py = PY - 2 + hh / PX;
+                px = hh % PX;
+            } else {
+                const int hh = h - 4 * PX;
+                py = 2 + hh / 4;
+                const int c = hh % 4;
+                px = c < 2 ? c : PX - 4 + c;
+            }
+            hlds[j] = py * PX + px;
+            hoff[j] = wrap_int(y0 - 2 + py, ny) * nx + wrap_int(x0 - 2 + px, nx);
+        }
+    }
+    // ---- halo pressure cell: left column (x0-1, y0..) then bottom row (x0-1.., y0-1)
+    int hp_off = -1, hp_q = 0, hp_c = 0;
+    if (tid < NHP) {
+        int qx, qy;
+        if (tid < TY) {
+            qx = 0;
+            qy = 1 + tid;
+        } else {
+            qx = tid - TY;
+            qy = 0;
+        }
+        hp_q = qy * (TX + 1) + qx;
+        hp_c = (qy + 1) * PX + (qx + 1);
+        hp_off = wrap_int(y0 - 1 + qy, ny) * nx + wrap_int(x0 - 1 + qx, nx);
+    }
+
+    // ---- register windows, primed for the prologue plane zz = z0 - 1
+    T Uw[5], Vw[5], Ww[3];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const int64_t zo = (int64_t)wrap_int(z0 - 3 + j, nz) * plane + own;
+        Uw[j] = Uin[zo];
+        Vw[j] = Vin[zo];
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Ww[j] = Win[(int64_t)wrap_int(z0 - 2 + j, nz) * plane + own];
+    int zcur = wrap_int(z0 - 1, nz);  // plane zz
+    int zA = wrap_int(z0 + 2, nz);    // zz + 3: next u, v window plane
+    int zB = wrap_int(z0 + 1, nz);    // zz + 2: next w window plane
+    int zC = wrap_int(z0, nz);        // zz + 1: next pressure / code plane
+    T pold = Pin[(int64_t)zcur * plane + own];
+    uint32_t code = 0;
+    T pn_prev = T(0);
+
+    double acc[kNumSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    __syncthreads();  // coefficient table
+
+    for (int zz = z0 - 1; zz < z1; ++zz) {
+        const bool body = zz >= z0;
+        const int64_t pbase = (int64_t)zcur * plane;
+        // prefetch the next window planes (used after this plane)
+        const bool more = zz + 1 < z1;
+        T nU = T(0), nV = T(0), nW = T(0), nP = T(0);
+        uint32_t nC = 0;
+        if (more) {
+            nU = Uin[(int64_t)zA * plane + own];
+            nV = Vin[(int64_t)zA * plane + own];
+            nW = Win[(int64_t)zB * plane + own];
+            nP = Pin[(int64_t)zC * plane + own];
+            nC = codes[(int64_t)zC * plane + own];
+        }
+
+        // ---- stage plane zz of u, v, w
+        sh.u[cl] = Uw[2];
+        sh.v[cl] = Vw[2];
+        sh.w[cl] = Ww[1];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            if (hoff[j] >= 0) {
+                sh.u[hlds[j]] = Uin[pbase + hoff[j]];
+                sh.v[hlds[j]] = Vin[pbase + hoff[j]];
+                sh.w[hlds[j]] = Win[pbase + hoff[j]];
+            }
+        T hp_w1 = T(0), hp_pold = T(0);
+        if (hp_off >= 0) {
+            hp_w1 = Win[(int64_t)zC * plane + hp_off];
+            hp_pold = Pin[pbase + hp_off];
+        }
+        __syncthreads();
+
+        // ---- pressure p^n of plane zz (tile and -x/-y halo)
+        T dvg = divergence(Uw[2], sh.u[cl + 1], Vw[2], sh.v[cl + PX], Ww[1], Ww[2]);
+        const T pn = skip ? pold : fma(-c2dt, dvg, pold);
+        sh.p[(ty + 1) * (TX + 1) + (tx + 1)] = pn;
+        if (hp_off >= 0) {
+            const T hd = divergence(sh.u[hp_c], sh.u[hp_c + 1], sh.v[hp_c], sh.v[hp_c + PX], sh.w[hp_c], hp_w1);
+            sh.p[hp_q] = skip ? hp_pold : fma(-c2dt, hd, hp_pold);
+        }
+        if (body && active) {
+            Pout[pbase + own] = pn;
+            if (reduce) {
+                const double nd = (double)(nu * dvg);
+                acc[1] += nd * nd;
+            }
+        }
+        __syncthreads();
+
+        // ---- velocity v^{n+1} of plane zz
+        if (body && active) {
+            const int pq = (ty + 1) * (TX + 1) + (tx + 1);
+            const T pc = sh.p[pq];
+            // u: own axis x, across y (LDS) and z (registers)
+            const uint32_t cu = code;
+            const T u0 = Uw[2];
+            const T u_d2x = d2_own(sh.u[cl - 1], u0, sh.u[cl + 1]);
+            const T u_d2y = d2_perp(sh.tab[cu & 7], sh.u[cl - 2 * PX], sh.u[cl - PX], u0, sh.u[cl + PX],
+                                    sh.u[cl + 2 * PX]);
+            const T u_d2z = d2_perp(sh.tab[(cu >> 3) & 7], Uw[0], Uw[1], u0, Uw[3], Uw[4]);
+            const T Fu = momentum(u_d2x, u_d2y, u_d2z, pc, sh.p[pq - 1], nu, gu);
+            const bool su = (cu & kSolidBit) != 0;
+            Uout[pbase + own] = su ? T(0) : fma(dt, Fu, u0);
+            // v: own axis y, across x (LDS) and z (registers)
+            const uint32_t cv = code >> kCodeBits;
+            const T v0 = Vw[2];
+            const T v_d2x = d2_perp(sh.tab[cv & 7], sh.v[cl - 2], sh.v[cl - 1], v0, sh.v[cl + 1], sh.v[cl + 2]);
+            const T v_d2y = d2_own(sh.v[cl - PX], v0, sh.v[cl + PX]);
+            const T v_d2z = d2_perp(sh.tab[(cv >> 3) & 7], Vw[0], Vw[1], v0, Vw[3], Vw[4]);
+            const T Fv = momentum(v_d2x, v_d2y, v_d2z, pc, sh.p[pq - (TX + 1)], nu, gv);
+            const bool sv = (cv & kSolidBit) != 0;
+            Vout[pbase + own] = sv ? T(0) : fma(dt, Fv, v0);
+            // w: own axis z (registers), across x and y (LDS)
+            const uint32_t cw = code >> (2 * kCodeBits);
+            const T w0 = Ww[1];
+            const T w_d2x = d2_perp(sh.tab[cw & 7], sh.w[cl - 2], sh.w[cl - 1], w0, sh.w[cl + 1], sh.w[cl + 2]);
+            const T w_d2y = d2_perp(sh.tab[(cw >> 3) & 7], sh.w[cl - 2 * PX], sh.w[cl - PX], w0,
+                                    sh.w[cl + PX], sh.w[cl + 2 * PX]);
+            const T w_d2z = d2_own(Ww[0], w0, Ww[2]);
+            const T Fw = momentum(w_d2x, w_d2y, w_d2z, pn, pn_prev, nu, gw);
+            const bool sw = (cw & kSolidBit) != 0;
+            Wout[pbase + own] = sw ? T(0) : fma(dt, Fw, w0);
+            if (reduce) {
+                const double fu = su ? 0.0 : (double)Fu, fv = sv ? 0.0 : (double)Fv,
+                             fw = sw ? 0.0 : (double)Fw;
+                acc[0] += fu * fu + fv * fv + fw * fw;
+                acc[2] += (double)u0;
+                acc[3] += (double)v0;
+                acc[4] += (double)w0;
+            }
+        }
+        __syncthreads();
+
+        // ---- advance the windows
+        pn_prev = pn;
+        if (more) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                Uw[j] = Uw[j + 1];
+                Vw[j] = Vw[j + 1];
+            }
+            Uw[4] = nU;
+            Vw[4] = nV;
+            Ww[0] = Ww[1];
+            Ww[1] = Ww[2];
+            Ww[2] = nW;
+            pold = nP;
+            code = nC;
+            zcur = zC;
+            zC = zB;
+            zB = zA;
+            zA = (zA + 1 == nz) ? 0 : zA + 1;
+        }
+    }
+    if (reduce) block_sums(acc, sh.red, I.partials + lb * kNumSums);
+}
+
+bool fused_tile_supported(int tx, int ty)
+{
+    return (tx == 64 && (ty == 4 || ty == 8 || ty == 16)) || (tx == 32 && (ty == 8 || ty == 16));
+}
+
+template <typename T>
+static hipError_t launch_fused_t(int tx, int ty, const InstDev *insts, int ninst, int64_t nblocks, int parity,
+                                 int reduce, hipStream_t s)
+{
+    const dim3 grid((unsigned)nblocks);
+#define PS_FUSED_CASE(TX_, TY_)                                                                             \
+    if (tx == TX_ && ty == TY_) {                                                                          \
+        hipLaunchKernelGGL((k_fused<T, TX_, TY_>), grid, dim3(TX_ * TY_), 0, s, insts, ninst, parity,     \
+                           reduce);                                                                        \
+        return hipGetLastError();                                                                          \
+    }
+    PS_FUSED_CASE(64, 4)
+    PS_FUSED_CASE(64, 8)
+    PS_FUSED_CASE(64, 16)
+    PS_FUSED_CASE(32, 8)
+    PS_FUSED_CASE(32, 16)
+#undef PS_FUSED_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fused(Prec prec, int tx, int ty, const InstDev *insts, int ninst, int64_t nblocks, int parity,
+                        int reduce, hipStream_t s)
+{
+    if (nblocks <= 0 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    return prec == kF64 ? launch_fused_t<double>(tx, ty, insts, ninst, nblocks, parity, reduce, s)
+                        : launch_fused_t<float>(tx, ty, insts, ninst, nblocks, parity, reduce, s);
+}
+
+// ============================================================== reductions
+
+__global__ void k_reduce_partials(const PartialRef *__restrict__ refs, double *__restrict__ out)
+{
+    __shared__ double scratch[kNumSums * 4];
+    const PartialRef r = refs[blockIdx.x];
+    double acc[kNumSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = threadIdx.x; i < r.nblocks; i += blockDim.x)
+#pragma unroll
+        for (int j = 0; j < kNumSums; ++j) acc[j] += r.partials[i * kNumSums + j];
+    block_sums(acc, scratch, out + (int64_t)blockIdx.x * kNumSums);
+}
+
+hipError_t launch_reduce_partials(const PartialRef *refs, int ninst, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_partials, dim3(ninst), dim3(256), 0, s, refs, out);
+    return hipGetLastError();
+}
+
+// ============================================================== simple sweep
+//
+// Velocity pass: one thread per cell updates its three faces from (v^n, p^n);
+// pressure pass: p^{n+1} = p^n - c2 dt div(v^{n+1}).  Same per-face routines as
+// the fused kernel; all neighbours come straight from global memory.
+
+template <typename T>
+__device__ __forceinline__ T ld(const T *__restrict__ f, int nx, int ny, int nz, int x, int y, int z)
+{
+    return f[((int64_t)wrap_small(z, nz) * ny + wrap_small(y, ny)) * nx + wrap_small(x, nx)];
+}
+
+template <typename T>
+__global__ void k_simple_vel(int nx, int ny, int nz, int axis, const uint32_t *__restrict__ codes,
+                             const T *__restrict__ U, const T *__restrict__ V, const T *__restrict__ W,
+                             const T *__restrict__ P, T *__restrict__ Uo, T *__restrict__ Vo, T *__restrict__ Wo,
+                             T nu, T dt, T drive)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int x = (int)(t % nx), y = (int)((t / nx) % ny), z = (int)(t / ((int64_t)nx * ny));
+    const uint32_t code = codes[t];
+    const T pc = P[t];
+    {
+        const uint32_t c = code;
+        const T v0 = U[t];
+        const T d2x = d2_own(ld(U, nx, ny, nz, x - 1, y, z), v0, ld(U, nx, ny, nz, x + 1, y, z));
+        const T d2y = d2_perp(coef_of_code<T>(c & 7), ld(U, nx, ny, nz, x, y - 2, z), ld(U, nx, ny, nz, x, y - 1, z),
+                              v0, ld(U, nx, ny, nz, x, y + 1, z), ld(U, nx, ny, nz, x, y + 2, z));
+        const T d2z = d2_perp(coef_of_code<T>((c >> 3) & 7), ld(U, nx, ny, nz, x, y, z - 2),
+                              ld(U, nx, ny, nz, x, y, z - 1), v0, ld(U, nx, ny, nz, x, y, z + 1),
+                              ld(U, nx, ny, nz, x, y, z + 2));
+        const T F = momentum(d2x, d2y, d2z, pc, ld(P, nx, ny, nz, x - 1, y, z), nu, axis == 0 ? drive : T(0));
+        Uo[t] = (c & kSolidBit) ? T(0) : fma(dt, F, v0);
+    }
+    {
+        const uint32_t c = code >> kCodeBits;
+        const T v0 = V[t];
+        const T d2x = d2_perp(coef_of_code<T>(c & 7), ld(V, nx, ny, nz, x - 2, y, z), ld(V, nx, ny, nz, x - 1, y, z),
+                              v0, ld(V, nx, ny, nz, x + 1, y, z), ld(V, nx, ny, nz, x + 2, y, z));
+        const T d2y = d2_own(ld(V, nx, ny, nz, x, y - 1, z), v0, ld(V, nx, ny, nz, x, y + 1, z));
+        const T d2z = d2_perp(coef_of_code<T>((c >> 3) & 7), ld(V, nx, ny, nz, x, y, z - 2),
+                              ld(V, nx, ny, nz, x, y, z - 1), v0, ld(V, nx, ny, nz, x, y, z + 1),
+                              ld(V, nx, ny, nz, x, y, z + 2));
+        const T F = momentum(d2x, d2y, d2z, pc, ld(P, nx, ny, nz, x, y - 1, z), nu, axis == 1 ? drive : T(0));
+        Vo[t] = (c & kSolidBit) ? T(0) : fma(dt, F, v0);
+    }
+    {
+        const uint32_t c = code >> (2 * kCodeBits);
+        const T v0 = W[t];
+        const T d2x = d2_perp(coef_of_code<T>(c & 7), ld(W, nx, ny, nz, x - 2, y, z), ld(W, nx, ny, nz, x - 1, y, z),
+                              v0, ld(W, nx, ny, nz, x + 1, y, z), ld(W, nx, ny, nz, x + 2, y, z));
+        const T d2y = d2_perp(coef_of_code<T>((c >> 3) & 7), ld(W, nx, ny, nz, x, y - 2, z),
+                              ld(W, nx, ny, nz, x, y - 1, z), v0, ld(W, nx, ny, nz, x, y + 1, z),
+                              ld(W, nx, ny, nz, x, y + 2, z));
+        const T d2z = d2_own(ld(W, nx, ny, nz, x, y, z - 1), v0, ld(W, nx, ny, nz, x, y, z + 1));
+        const T F = momentum(d2x, d2y, d2z, pc, ld(P, nx, ny, nz, x, y, z - 1), nu, axis == 2 ? drive : T(0));
+        Wo[t] = (c & kSolidBit) ? T(0) : fma(dt, F, v0);
+    }
+}
+
+template <typename T>
+__global__ void k_simple_pres(int nx, int ny, int nz, const T *__restrict__ U, const T *__restrict__ V,
+                              const T *__restrict__ W, const T *__restrict__ P, T *__restrict__ Po, T c2dt)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int x = (int)(t % nx), y = (int)((t / nx) % ny), z = (int)(t / ((int64_t)nx * ny));
+    const T d = divergence(U[t], ld(U, nx, ny, nz, x + 1, y, z), V[t], ld(V, nx, ny, nz, x, y + 1, z), W[t],
+                           ld(W, nx, ny, nz, x, y, z + 1));
+    Po[t] = fma(-c2dt, d, P[t]);
+}
+
+template <typename T>
+static hipError_t simple_sweep_t(int nx, int ny, int nz, int axis, const uint32_t *codes, const void *const in[4],
+                                 void *const out[4], double nu, double dt, double c2dt, double drive, hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    hipLaunchKernelGGL(k_simple_vel<T>, dim3(grid1d(n, 256)), dim3(256), 0, s, nx, ny, nz, axis, codes,
+                       (const T *)in[0], (const T *)in[1], (const T *)in[2], (const T *)in[3], (T *)out[0],
+                       (T *)out[1], (T *)out[2], (T)nu, (T)dt, (T)drive);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_simple_pres<T>, dim3(grid1d(n, 256)), dim3(256), 0, s, nx, ny, nz, (const T *)out[0],
+                       (const T *)out[1], (const T *)out[2], (const T *)in[3], (T *)out[3], (T)c2dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_simple_sweep(Prec prec, int nx, int ny, int nz, int axis, const uint32_t *codes,
+                               const void *const in[4], void *const out[4], double nu, double dt, double c2dt,
+                               double drive, hipStream_t s)
+{
+    return prec == kF64 ? simple_sweep_t<double>(nx, ny, nz, axis, codes, in, out, nu, dt, c2dt, drive, s)
+                        : simple_sweep_t<float>(nx, ny, nz, axis, codes, in, out, nu, dt, c2dt, drive, s);
+}
+
+// ============================================================== state sums
+//
+// S_F, S_D and the face sums of a state (v, p), one thread per cell, FP64
+// accumulation, per-block partials reduced afterwards in a fixed order.
+
+constexpr int kSumsBlock = 256;
+constexpr int64_t kSumsMaxBlocks = 8192;
+
+int64_t state_sums_blocks(int64_t n)
+{
+    int64_t b = (n + kSumsBlock - 1) / kSumsBlock;
+    return b < kSumsMaxBlocks ? b : kSumsMaxBlocks;
+}
+
+template <typename T>
+__global__ void k_state_sums(int nx, int ny, int nz, int axis, const uint32_t *__restrict__ codes,
+                             const T *__restrict__ U, const T *__restrict__ V, const T *__restrict__ W,
+                             const T *__restrict__ P, T nu, T drive, double *__restrict__ partials)
+{
+    __shared__ double scratch[kNumSums * (kSumsBlock / 64)];
+    const int64_t n = (int64_t)nx * ny * nz;
+    double acc[kNumSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(t % nx), y = (int)((t / nx) % ny), z = (int)(t / ((int64_t)nx * ny));
+        const uint32_t code = codes[t];
+        const T pc = P[t];
+        const T* F3[3] = {U, V, W};
+        for (int k = 0; k < 3; ++k) {
+            const uint32_t c = code >> (kCodeBits * k);
+            const T *f = F3[k];
+            const T v0 = f[t];
+            acc[2 + k] += (double)v0;
+            if (c & kSolidBit) continue;
+            T d2[3];
+            const int i1 = (k == 0) ? 1 : 0;  // first perpendicular axis
+            for (int i = 0; i < 3; ++i) {
+                int q[3] = {x, y, z};
+                auto at = [&](int d) {
+                    int r[3] = {q[0], q[1], q[2]};
+                    r[i] += d;
+                    return ld(f, nx, ny, nz, r[0], r[1], r[2]);
+                };
+                if (i == k) d2[i] = d2_own(at(-1), v0, at(1));
+                else {
+                    const int sh = (i == i1) ? 0 : 3;
+                    d2[i] = d2_perp(coef_of_code<T>((c >> sh) & 7), at(-2), at(-1), v0, at(1), at(2));
+                }
+            }
+            int q[3] = {x, y, z};
+            q[k] -= 1;
+            const T pm = ld(P, nx, ny, nz, q[0], q[1], q[2]);
+            const T F = momentum(d2[0], d2[1], d2[2], pc, pm, nu, k == axis ? drive : T(0));
+            acc[0] += (double)F * (double)F;
+        }
+        const T d = divergence(U[t], ld(U, nx, ny, nz, x + 1, y, z), V[t], ld(V, nx, ny, nz, x, y + 1, z), W[t],
+                               ld(W, nx, ny, nz, x, y, z + 1));
+        const double nd = (double)(nu * d);
+        acc[1] += nd * nd;
+    }
+    block_sums(acc, scratch, partials + (int64_t)blockIdx.x * kNumSums);
+}
+
+hipError_t launch_state_sums(Prec prec, int nx, int ny, int nz, int axis, const uint32_t *codes,
+                             const void *const st[4], double nu, double drive, double *partials, int64_t *nblocks,
+                             hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int64_t nb = state_sums_blocks(n);
+    *nblocks = nb;
+    if (prec == kF64)
+        hipLaunchKernelGGL(k_state_sums<double>, dim3((unsigned)nb), dim3(kSumsBlock), 0, s, nx, ny, nz, axis,
+                           codes, (const double *)st[0], (const double *)st[1], (const double *)st[2],
+                           (const double *)st[3], nu, drive, partials);
+    else
+        hipLaunchKernelGGL(k_state_sums<float>, dim3((unsigned)nb), dim3(kSumsBlock), 0, s, nx, ny, nz, axis,
+                           codes, (const float *)st[0], (const float *)st[1], (const float *)st[2],
+                           (const float *)st[3], (float)nu, (float)drive, partials);
+    return hipGetLastError();
+}
+
+}  // namespace ps

@@ -1,0 +1,267 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars (from the method's arithmetic):
+  * face flags and stencil codes: bit-exact;
+  * kernel variants (tiles, z-chunks, batched, two-pass): bitwise identical iterates;
+  * FP64 iterate after N sweeps: <= 1e-12 relative (max-norm over each field);
+  * FP64 converged k: <= 1e-10 relative, normwise |dk_ij| / max|k|, same sweep count;
+  * FP32 (+ FP64 defect correction) converged k: <= 1e-5 relative, normwise.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2407_19868_amd as ps
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch.cuda.set_device(0)
+    c = ps.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def random_state(mask, seed, scale=1e-2):
+    rng = np.random.default_rng(seed)
+    fs = oracle.face_solid(mask)
+    st = oracle.State(*(rng.standard_normal(mask.shape) * scale for _ in range(4)))
+    st.u[fs[0] == 1] = 0
+    st.v[fs[1] == 1] = 0
+    st.w[fs[2] == 1] = 0
+    return st
+
+
+MASKS = {
+    "spheres_12x10x9": lambda: synth.spheres(12, 10, 9, 2.0, 2.5, 0.5, 7),
+    "spheres_70x13x11": lambda: synth.spheres(70, 13, 11, 2.0, 3.0, 0.55, 8),
+    "extruded_16x16x1": lambda: synth.test_grid(101),
+    "thin_3x2x5": lambda: synth.spheres(3, 2, 5, 0.8, 0.8, 0.7, 9),
+    "one_cell_x": lambda: np.ascontiguousarray(synth.spheres(1, 9, 8, 1.5, 1.5, 0.6, 10)),
+    "ragged_33x17x6": lambda: synth.spheres(33, 17, 6, 1.5, 2.5, 0.55, 11),
+}
+
+
+# ------------------------------------------------------------ preprocessing
+
+@pytest.mark.parametrize("name", sorted(MASKS))
+def test_face_bits_bit_exact(ctx, name):
+    mask = MASKS[name]()
+    bits = ctx.preprocess(ps.to_device(mask))
+    want = oracle.pack_bits(oracle.face_solid(mask))
+    got = bits.cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("name", sorted(MASKS))
+def test_face_codes_match_oracle_classifier(ctx, name):
+    mask = MASKS[name]()
+    codes = ctx.face_codes(ps.to_device(mask)).cpu().numpy().view(np.uint32)
+    fs = oracle.face_solid(mask)
+    nz, ny, nx = mask.shape
+    perp = {0: (1, 2), 1: (0, 2), 2: (0, 1)}
+    # case number of a 3-bit code L | R<<1 | F<<2
+    code_case = {0: 6, 1: 4, 2: 5, 3: 1, 5: 2, 6: 3}
+    for k in range(3):
+        c = (codes >> np.uint32(8 * k)) & np.uint32(0x7F)
+        assert np.array_equal((c >> np.uint32(6)) & np.uint32(1), fs[k].astype(np.uint32))
+        for slot, i in enumerate(perp[k]):
+            code = (c >> np.uint32(3 * slot)) & np.uint32(7)
+            ax = 2 - i
+            s = [np.roll(fs[k], -d, axis=ax) for d in (-2, -1, 1, 2)]
+            for z in range(nz):
+                for y in range(ny):
+                    for x in range(nx):
+                        want = oracle.case(s[0][z, y, x], s[1][z, y, x], s[2][z, y, x], s[3][z, y, x])
+                        got = code_case.get(int(code[z, y, x]), -1)
+                        assert got == want, (k, i, x, y, z, int(code[z, y, x]))
+
+
+# ------------------------------------------------------------ sweeps
+
+def gpu_iterate(ctx, mask, axis, st, count, prec=ps.FP64, **kw):
+    dtype = torch.float64 if prec == ps.FP64 else torch.float32
+    f = [dev(a, dtype) for a in st.arrays()]
+    ctx.iterate(ps.to_device(mask), axis, f, count, ps.params(precision=prec, **kw))
+    torch.cuda.synchronize()
+    return [host(t) for t in f]
+
+
+@pytest.mark.parametrize("name", sorted(MASKS))
+@pytest.mark.parametrize("count", [1, 2, 7])
+def test_iterate_fp64_against_oracle(ctx, name, count):
+    mask = MASKS[name]()
+    axis = count % 3
+    st = random_state(mask, 17 + count)
+    prm = oracle.params()
+    want = st
+    for _ in range(count):
+        want = oracle.sweep(mask, axis, want, prm)
+    got = gpu_iterate(ctx, mask, axis, st, count)
+    for g, w in zip(got, want.arrays()):
+        scale = max(np.abs(w).max(), 1e-300)
+        assert np.abs(g - w).max() / scale <= 1e-12
+
+
+TILES = [(64, 8, 0), (64, 4, 3), (64, 16, 1), (32, 8, 5), (32, 16, 2), (64, 8, 64)]
+
+
+@pytest.mark.parametrize("name", ["spheres_70x13x11", "ragged_33x17x6", "thin_3x2x5", "extruded_16x16x1"])
+@pytest.mark.parametrize("prec", [ps.FP64, ps.FP32])
+def test_kernel_variants_bitwise(ctx, name, prec):
+    """Every tile / z-chunk of the fused kernel and the two-pass kernel give
+    bitwise identical iterates (a race or halo error would break this)."""
+    mask = MASKS[name]()
+    st = random_state(mask, 5)
+    ref = gpu_iterate(ctx, mask, 1, st, 9, prec, kernel=ps.KERNEL_SIMPLE)
+    for tx, ty, zc in TILES:
+        got = gpu_iterate(ctx, mask, 1, st, 9, prec, kernel=ps.KERNEL_FUSED, tile_x=tx, tile_y=ty,
+                          zchunk=zc)
+        for g, r in zip(got, ref):
+            assert np.array_equal(g, r), (tx, ty, zc)
+
+
+def test_iterate_fp32_against_oracle(ctx):
+    mask = MASKS["spheres_70x13x11"]()
+    st = random_state(mask, 3)
+    want = st
+    for _ in range(5):
+        want = oracle.sweep(mask, 0, want, oracle.params())
+    got = gpu_iterate(ctx, mask, 0, st, 5, ps.FP32)
+    for g, w in zip(got, want.arrays()):
+        assert np.abs(g - w).max() / np.abs(w).max() < 1e-5
+
+
+@pytest.mark.parametrize("name", sorted(MASKS))
+def test_residual_sums_against_oracle(ctx, name):
+    mask = MASKS[name]()
+    st = random_state(mask, 23)
+    axis = len(name) % 3
+    got = ctx.residual(ps.to_device(mask), axis, [dev(a) for a in st.arrays()])
+    want = oracle.state_sums(mask, axis, st)
+    assert got[0] == pytest.approx(want[0], rel=1e-12)
+    assert got[1] == pytest.approx(want[1], rel=1e-12)
+    scale = max(abs(want[2:]).max(), 1e-300)
+    assert np.abs(got[2:] - want[2:]).max() / scale < 1e-12
+
+
+# ------------------------------------------------------------ solves
+
+def normwise(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("seed", range(100, 110))
+def test_solve_fp64_test_grids(ctx, seed):
+    mask = synth.test_grid(seed)
+    axis = seed % 3
+    g = ctx.solve(ps.to_device(mask), axis, ps.params())
+    o = oracle.solve(mask, axis, oracle.params())
+    assert g.status == o.status == "OK"
+    assert g.sweeps == o.sweeps
+    assert normwise(g.kcol, o.kcol) <= 1e-10
+    assert np.array_equal(g.hist_sweep, o.hist_sweep)
+    assert np.allclose(g.hist_r, o.hist_r, rtol=1e-9, atol=0)
+    # fields of the returned state
+    for gf, of in zip(g.fields, o.state.arrays()):
+        assert np.abs(host(gf) - of).max() / max(np.abs(of).max(), 1e-300) < 1e-8
+
+
+def test_solve_fp64_single_spheres_32(ctx):
+    """32^3 packing, radius 4, porosity 0.40, seed 1, load along x, tol 1e-8."""
+    mask = synth.single_spheres_32()
+    g = ctx.solve(ps.to_device(mask), 0, ps.params())
+    o = oracle.solve(mask, 0, oracle.params())
+    assert g.status == o.status == "OK"
+    assert g.sweeps == o.sweeps
+    assert normwise(g.kcol, o.kcol) <= 1e-10
+
+
+@pytest.mark.parametrize("seed", [100, 101, 102])
+def test_solve_fp32_dc_against_fp64_oracle(ctx, seed):
+    mask = synth.test_grid(seed)
+    axis = seed % 3
+    g = ctx.solve(ps.to_device(mask), axis, ps.params(precision=ps.FP32_DC))
+    o = oracle.solve(mask, axis, oracle.params())
+    assert g.status == "OK"
+    assert normwise(g.kcol, o.kcol) <= 1e-5
+    assert g.hist_r[-1] < 1e-8
+
+
+def test_tensor_against_oracle(ctx):
+    mask = synth.spheres(16, 14, 12, 2.0, 3.0, 0.5, 55)
+    g = ctx.tensor(ps.to_device(mask), ps.params())
+    k, ksym, _ = oracle.tensor(mask, oracle.params())
+    assert g.status == "OK"
+    assert normwise(g.k, k) <= 1e-10
+    assert np.allclose(g.k_sym, 0.5 * (g.k + g.k.T), rtol=0, atol=0)
+
+
+def test_batch_equals_single_solves(ctx):
+    masks = [synth.spheres(20, 18, 16, 2.0, 3.0, 0.5, 60 + i) for i in range(3)]
+    masks.append(synth.spheres(33, 9, 14, 1.5, 2.5, 0.55, 64))
+    probs = [(ps.to_device(m), i % 3) for i, m in enumerate(masks)]
+    st, res = ctx.solve_batch(probs, ps.params())
+    assert st == "OK"
+    for (m, axis), r in zip(probs, res):
+        single = ctx.solve(m, axis, ps.params())
+        assert r["status"] == single.status == "OK"
+        assert r["sweeps"] == single.sweeps
+        assert np.array_equal(r["kcol"], single.kcol)
+
+
+# ------------------------------------------------------------ stop rules and errors
+
+def test_not_converged_history(ctx):
+    mask = synth.spheres(10, 10, 10, 2.5, 2.5, 0.5, 81)
+    g = ctx.solve(ps.to_device(mask), 0, ps.params(max_sweeps=250))
+    o = oracle.solve(mask, 0, oracle.params(max_sweeps=250))
+    assert g.status == o.status == "NOT_CONVERGED"
+    assert g.sweeps == 250
+    assert list(g.hist_sweep) == [0, 100, 200, 250]
+    assert normwise(g.kcol, o.kcol) <= 1e-10
+
+
+def test_diverged(ctx):
+    mask = synth.spheres(10, 10, 10, 2.5, 2.5, 0.5, 81)
+    g = ctx.solve(ps.to_device(mask), 0, ps.params(dt=2.0 ** -10, check_every=20, max_sweeps=20000))
+    assert g.status == "DIVERGED"
+
+
+def test_no_flow(ctx):
+    solid = np.ones((4, 4, 4), dtype=np.uint8)
+    assert ctx.solve(ps.to_device(solid), 0).status == "NO_FLOW"
+    fluid = np.zeros((4, 4, 4), dtype=np.uint8)
+    assert ctx.solve(ps.to_device(fluid), 0).status == "NO_FLOW"
+    striped = np.zeros((4, 4, 4), dtype=np.uint8)
+    striped[:, :, ::2] = 1
+    assert ctx.solve(ps.to_device(striped), 0).status == "NO_FLOW"
+
+
+def test_argument_errors(ctx):
+    m = ps.to_device(synth.spheres(8, 8, 8, 2.0, 2.0, 0.5, 1))
+    with pytest.raises(ps.PorestokesError, match="ERR_ARG"):
+        ctx.solve(m, 3)
+    with pytest.raises(ps.PorestokesError, match="ERR_ARG"):
+        ctx.solve(m, 0, ps.params(tile_x=48, tile_y=8))
+    with pytest.raises(ps.PorestokesError, match="ERR_ARG"):
+        ctx.solve(m, 0, ps.params(dt=-1.0))
+
+
+def test_memory_cap(ctx):
+    m = ps.to_device(synth.spheres(16, 16, 16, 2.0, 2.0, 0.5, 1))
+    with ps.Context(0, mem_cap=4096) as small:
+        with pytest.raises(ps.PorestokesError, match="ERR_OOM"):
+            small.solve(m, 0)
