@@ -220,6 +220,21 @@ typedef struct {
 pm_status pm_solve_batch(pm_ctx *ctx, void *stream, pm_instance *inst, int32_t n,
                          const pm_params *params);
 
+/* Timing of the sweep kernels of the last pm_iterate / pm_solve / pm_tensor /
+ * pm_solve_batch call on a context, measured with HIP events recorded on the
+ * call's stream around each run of consecutive sweep launches. */
+typedef struct {
+    int64_t sweep_launches;  /* sweep-kernel launches                                  */
+    int64_t voxel_updates;   /* voxels swept, summed over launches (all instances)     */
+    double sweep_ms;         /* GPU time spanned by those launches                     */
+    double total_ms;         /* host wall time of the call                             */
+    int32_t tile_x, tile_y, zchunk;  /* decomposition of the last instance             */
+    int32_t precision;       /* pm_precision of the last sweep launch (PM_FP64/PM_FP32) */
+} pm_stats;
+
+/* Copy the statistics of the last call into *out (host). */
+pm_status pm_last_stats(const pm_ctx *ctx, pm_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

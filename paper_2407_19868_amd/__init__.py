@@ -29,7 +29,7 @@ KERNEL_AUTO, KERNEL_FUSED, KERNEL_SIMPLE = 0, 1, 2
 # Every symbol declared in include/porestokes.h.
 EXPORTS = ("pm_params_default", "pm_status_string", "pm_create", "pm_destroy", "pm_last_error",
            "pm_mem_used", "pm_preprocess", "pm_face_codes", "pm_iterate", "pm_residual", "pm_solve",
-           "pm_tensor", "pm_solve_batch")
+           "pm_tensor", "pm_solve_batch", "pm_last_stats")
 
 
 class PmParams(ctypes.Structure):
@@ -85,6 +85,19 @@ class PmInstance(ctypes.Structure):
     ]
 
 
+class PmStats(ctypes.Structure):
+    _fields_ = [
+        ("sweep_launches", ctypes.c_int64),
+        ("voxel_updates", ctypes.c_int64),
+        ("sweep_ms", ctypes.c_double),
+        ("total_ms", ctypes.c_double),
+        ("tile_x", ctypes.c_int32),
+        ("tile_y", ctypes.c_int32),
+        ("zchunk", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+    ]
+
+
 _lib = None
 
 
@@ -127,6 +140,8 @@ def load_library(path: str = LIB_PATH):
     lib.pm_tensor.restype = i32
     lib.pm_solve_batch.argtypes = [vp, vp, ctypes.POINTER(PmInstance), ctypes.c_int32, pp]
     lib.pm_solve_batch.restype = i32
+    lib.pm_last_stats.argtypes = [vp, ctypes.POINTER(PmStats)]
+    lib.pm_last_stats.restype = i32
     _lib = lib
     return lib
 
@@ -240,6 +255,12 @@ class Context:
 
     def mem_used(self) -> int:
         return int(self._lib.pm_mem_used(self._h))
+
+    def last_stats(self) -> dict:
+        """Sweep-kernel timing of the last call (HIP events on the call's stream)."""
+        st = PmStats()
+        self._check(self._lib.pm_last_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in PmStats._fields_}
 
     def _check(self, st: int, allow=(PM_OK,)):
         if st not in allow:

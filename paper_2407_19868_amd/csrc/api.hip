@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -29,6 +30,8 @@ struct pm_ctx {
     size_t h_sums_n = 0;
     std::map<std::string, std::vector<int>> tune;  // autotuned (tile_x, tile_y, zc) per shape key
     bool tune_loaded = false;
+    pm_stats stats{};
+    hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -120,6 +123,43 @@ pm_status ensure_host_sums(pm_ctx *ctx, size_t n)
 }
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void stats_begin(pm_ctx *ctx)
+{
+    std::memset(&ctx->stats, 0, sizeof ctx->stats);
+    ctx->stats.total_ms = -now_ms();
+}
+
+void stats_end(pm_ctx *ctx) { ctx->stats.total_ms += now_ms(); }
+
+pm_status ensure_events(pm_ctx *ctx)
+{
+    for (int i = 0; i < 2; ++i)
+        if (!ctx->ev[i]) PM_HIP(hipEventCreate(&ctx->ev[i]));
+    return PM_OK;
+}
+
+// Time a run of consecutive sweep launches: call with start=true before the
+// first launch and start=false after the last; accumulates into ctx->stats.
+pm_status stats_mark(pm_ctx *ctx, hipStream_t s, bool start, int64_t launches = 0, int64_t voxels = 0)
+{
+    PM_TRY(ensure_events(ctx));
+    PM_HIP(hipEventRecord(ctx->ev[start ? 0 : 1], s));
+    if (!start) {
+        PM_HIP(hipEventSynchronize(ctx->ev[1]));
+        float ms = 0.f;
+        PM_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+        ctx->stats.sweep_ms += ms;
+        ctx->stats.sweep_launches += launches;
+        ctx->stats.voxel_updates += voxels;
+    }
+    return PM_OK;
+}
 
 pm_status check_dims(pm_ctx *ctx, int64_t nx, int64_t ny, int64_t nz)
 {
@@ -430,10 +470,21 @@ struct Engine {
         PM_HIP(hipMemcpyAsync(d_tab, h_tab.data(), h_tab.size() * sizeof(InstDev), hipMemcpyHostToDevice, stream));
         PM_HIP(hipMemcpyAsync(d_refs, h_refs.data(), h_refs.size() * sizeof(PartialRef), hipMemcpyHostToDevice,
                               stream));
+        int64_t vox = 0;
+        for (int i : order) vox += inst[i].N;
+        PM_TRY(stats_mark(ctx, stream, true));
         for (int j = 0; j < steps; ++j)
             for (const Group &g : groups)
                 PM_HIP(launch_fused(g.prec, g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1,
                                     j == steps - 1 ? 1 : 0, stream));
+        PM_TRY(stats_mark(ctx, stream, false, (int64_t)steps * (int64_t)groups.size(), vox * steps));
+        {
+            const Inst &last = inst[order.back()];
+            ctx->stats.tile_x = last.tile.tx;
+            ctx->stats.tile_y = last.tile.ty;
+            ctx->stats.zchunk = last.tile.zc;
+            ctx->stats.precision = last.prec == kF64 ? PM_FP64 : PM_FP32;
+        }
         PM_HIP(launch_reduce_partials(d_refs, (int)order.size(), d_sums, stream));
         PM_HIP(hipMemcpyAsync(ctx->h_sums, d_sums, order.size() * kNumSums * sizeof(double),
                               hipMemcpyDeviceToHost, stream));
@@ -675,10 +726,19 @@ pm_status pm_create(int hip_device, size_t mem_cap_bytes, pm_ctx **out)
     return PM_OK;
 }
 
+pm_status pm_last_stats(const pm_ctx *ctx, pm_stats *out)
+{
+    if (!ctx || !out) return PM_ERR_ARG;
+    *out = ctx->stats;
+    return PM_OK;
+}
+
 void pm_destroy(pm_ctx *ctx)
 {
     if (!ctx) return;
     (void)hipSetDevice(ctx->dev);
+    for (int i = 0; i < 2; ++i)
+        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     for (auto &kv : ctx->allocs) (void)hipFree(kv.first);
     if (ctx->h_sums) (void)hipHostFree(ctx->h_sums);
     delete ctx;
@@ -727,6 +787,7 @@ pm_status pm_iterate(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx,
     if (count < 0) return fail(ctx, PM_ERR_ARG, "count must be >= 0");
     PM_TRY(set_device(ctx));
     hipStream_t s = (hipStream_t)stream;
+    stats_begin(ctx);
     if (count == 0) return PM_OK;
     const int64_t N = nx * ny * nz;
     Scratch scratch(ctx);
@@ -742,11 +803,13 @@ pm_status pm_iterate(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx,
     }
     const double nu = 1.0 / params->re, c2dt = params->c2 * params->dt;
     if (params->kernel == PM_KERNEL_SIMPLE) {
+        PM_TRY(stats_mark(ctx, s, true));
         for (int64_t n = 0; n < count; ++n) {
             const int a = (int)(n & 1);
             PM_HIP(launch_simple_sweep(prec, (int)nx, (int)ny, (int)nz, axis, (const uint32_t *)codes, set[a],
                                        set[a ^ 1], nu, params->dt, c2dt, params->drive, s));
         }
+        PM_TRY(stats_mark(ctx, s, false, 2 * count, count * N));
         if (count & 1)
             for (int k = 0; k < 4; ++k)
                 PM_HIP(hipMemcpyAsync(f[k], set[1][k], (size_t)N * elem(prec), hipMemcpyDeviceToDevice, s));
@@ -778,9 +841,15 @@ pm_status pm_iterate(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx,
     d[1].par_off = 1;  // sweeps K_1.. read set (n & 1) with launch parity j & 1 for n = j + 1
     PM_HIP(hipMemcpyAsync(tab, d, sizeof d, hipMemcpyHostToDevice, s));
     InstDev *dt = (InstDev *)tab;
+    PM_TRY(stats_mark(ctx, s, true));
     PM_HIP(launch_fused(prec, in.tile.tx, in.tile.ty, dt, 1, in.nblocks, 0, 0, s));
     for (int64_t n = 1; n <= count; ++n)
         PM_HIP(launch_fused(prec, in.tile.tx, in.tile.ty, dt + 1, 1, in.nblocks, (int)((n - 1) & 1), 0, s));
+    PM_TRY(stats_mark(ctx, s, false, count + 1, (count + 1) * N));
+    ctx->stats.tile_x = in.tile.tx;
+    ctx->stats.tile_y = in.tile.ty;
+    ctx->stats.zchunk = in.tile.zc;
+    ctx->stats.precision = prec == kF64 ? PM_FP64 : PM_FP32;
     const int vs = (int)(count & 1), ps_ = (int)((count + 1) & 1);
     if (vs)
         for (int k = 0; k < 3; ++k)
@@ -788,6 +857,7 @@ pm_status pm_iterate(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx,
     if (ps_) PM_HIP(hipMemcpyAsync(f[3], set[1][3], (size_t)N * elem(prec), hipMemcpyDeviceToDevice, s));
     // the scratch buffers are freed on return: finish the work that reads them
     PM_HIP(hipStreamSynchronize(s));
+    stats_end(ctx);
     return PM_OK;
 }
 
@@ -859,8 +929,13 @@ pm_status pm_solve_batch(pm_ctx *ctx, void *stream, pm_instance *insts, int32_t 
         if (in.hist) in.hist->n = 0;
     }
     PM_TRY(set_device(ctx));
-    Engine eng(ctx, (hipStream_t)stream, params, list);
-    pm_status rs = eng.run();
+    stats_begin(ctx);
+    pm_status rs;
+    {
+        Engine eng(ctx, (hipStream_t)stream, params, list);
+        rs = eng.run();
+    }
+    stats_end(ctx);
     pm_status worst = PM_OK;
     for (int i = 0; i < n; ++i) {
         pm_instance &pi = insts[i];

@@ -45,8 +45,8 @@ def test_struct_layouts_match_header():
 
     import paper_2407_19868_amd as ps
     src = ('#include "porestokes.h"\n#include <stdio.h>\n'
-           'int main(){printf("%zu %zu %zu\\n", sizeof(pm_params), sizeof(pm_history),'
-           ' sizeof(pm_instance));return 0;}\n')
+           'int main(){printf("%zu %zu %zu %zu\\n", sizeof(pm_params), sizeof(pm_history),'
+           ' sizeof(pm_instance), sizeof(pm_stats));return 0;}\n')
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
         exe = os.path.join(d, "t")
@@ -54,7 +54,7 @@ def test_struct_layouts_match_header():
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         sizes = [int(x) for x in subprocess.check_output([exe]).split()]
     assert sizes == [ctypes.sizeof(ps.PmParams), ctypes.sizeof(ps.PmHistory),
-                     ctypes.sizeof(ps.PmInstance)]
+                     ctypes.sizeof(ps.PmInstance), ctypes.sizeof(ps.PmStats)]
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

@@ -173,7 +173,9 @@ def test_solve_fp64_test_grids(ctx, seed):
     assert g.sweeps == o.sweeps
     assert normwise(g.kcol, o.kcol) <= 1e-10
     assert np.array_equal(g.hist_sweep, o.hist_sweep)
-    assert np.allclose(g.hist_r, o.hist_r, rtol=1e-9, atol=0)
+    # r is scaled so that r = 1 at rest; near convergence it differs by rounding
+    # of the iterate (absolute, relative to that scale)
+    assert np.allclose(g.hist_r, o.hist_r, rtol=1e-9, atol=1e-13)
     # fields of the returned state
     for gf, of in zip(g.fields, o.state.arrays()):
         assert np.abs(host(gf) - of).max() / max(np.abs(of).max(), 1e-300) < 1e-8
