@@ -183,8 +183,12 @@ pm_status check_params(pm_ctx *ctx, const pm_params *p)
     if (p->precision < PM_FP64 || p->precision > PM_FP32_DC) return fail(ctx, PM_ERR_ARG, "bad precision");
     if (p->stop_rule != 0 && p->stop_rule != 1) return fail(ctx, PM_ERR_ARG, "bad stop_rule");
     if (p->kernel < PM_KERNEL_AUTO || p->kernel > PM_KERNEL_SIMPLE) return fail(ctx, PM_ERR_ARG, "bad kernel");
-    if ((p->tile_x || p->tile_y) && !fused_tile_supported(p->tile_x, p->tile_y))
-        return fail(ctx, PM_ERR_ARG, "unsupported tile %dx%d", p->tile_x, p->tile_y);
+    if (p->tile_x || p->tile_y) {
+        const bool f64 = p->precision != PM_FP32, f32 = p->precision != PM_FP64;
+        if ((f64 && !fused_tile_supported(p->tile_x, p->tile_y, kF64)) ||
+            (f32 && !fused_tile_supported(p->tile_x, p->tile_y, kF32)))
+            return fail(ctx, PM_ERR_ARG, "unsupported tile %dx%d for this precision", p->tile_x, p->tile_y);
+    }
     if (p->zchunk < 0) return fail(ctx, PM_ERR_ARG, "zchunk must be >= 0");
     return PM_OK;
 }

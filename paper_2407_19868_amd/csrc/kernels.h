@@ -47,7 +47,7 @@ hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream
 // Fused sweep over the instances of a device table (all of precision prec).
 hipError_t launch_fused(Prec prec, int tile_x, int tile_y, const InstDev *insts, int ninst,
                         int64_t nblocks, int parity, int reduce, hipStream_t s);
-bool fused_tile_supported(int tile_x, int tile_y);
+bool fused_tile_supported(int tile_x, int tile_y, int prec);
 
 // Final deterministic reduction: out[i * kNumSums + j] = sum over blocks of refs[i].
 hipError_t launch_reduce_partials(const PartialRef *refs, int ninst, double *out, hipStream_t s);

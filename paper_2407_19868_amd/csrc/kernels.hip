@@ -8,6 +8,8 @@
 #include "common.h"
 #include "kernels.h"
 
+#define GLOBAL_AS __attribute__((address_space(1)))
+
 namespace ps {
 
 // ============================================================== preprocessing
@@ -197,20 +199,24 @@ hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream
 // the state (v^n, p^n) -- F(v^n, p^n) and div v^n -- falls out of the same pass.
 //
 // Work decomposition: a workgroup owns a TX x TY column tile of the x-y plane
-// and a chunk of zc planes, streamed bottom to top.  Per plane the velocity
-// fields are staged in LDS with a 2-cell halo (the App. B stencils reach two
-// faces across the flow); the planes above and below each thread's own column
-// stay in a register window (5 planes for u and v, 3 for w).  The pressure of
-// the plane is computed for the tile plus a one-cell halo at -x and -y (the
-// pressure gradient of a face reads the cell behind it) and kept in LDS.
+// and a chunk of zc planes, streamed bottom to top, one thread per column.
+// Per plane, u, v and p^{n-1} are staged in LDS with a two-cell halo (the
+// App. B stencils reach two faces across the flow); w is staged one plane
+// ahead.  The planes above and below each thread's own column stay in a
+// register window (5 planes of u and v, 3 of w).  Each thread computes p^n of
+// its own cell and of its -x and -y neighbours (the pressure gradient of a
+// face reads the cell behind it), so pressures are never exchanged.  LDS
+// slots rotate (u, v, p over 2 planes, w over 3), which leaves one barrier
+// per plane, and every global load -- own column and halo -- is issued one
+// plane before it is needed.
 
 template <typename T, int TX, int TY>
 struct FusedShared {
-    static constexpr int PX = TX + 4, PY = TY + 4;
-    T u[PY * PX];
-    T v[PY * PX];
-    T w[PY * PX];
-    T p[(TY + 1) * (TX + 1)];
+    static constexpr int PX = TX + 4, PY = TY + 4, PP = PX * PY;
+    T u[2][PP];
+    T v[2][PP];
+    T p[2][PP];
+    T w[3][PP];
     Coef<T> tab[8];
     double red[kNumSums * (TX * TY / 64)];
 };
@@ -222,9 +228,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
     constexpr int NT = TX * TY;
     constexpr int PX = TX + 4, PY = TY + 4;
     constexpr int NHALO = PX * PY - NT;
-    constexpr int NHP = TX + TY + 1;
-    static_assert(NHALO <= 2 * NT, "halo too large for two loads per thread");
-    static_assert(NHP <= NT, "pressure halo larger than the block");
+    static_assert(NHALO <= NT, "one halo position per thread");
     __shared__ FusedShared<T, TX, TY> sh;
 
     // ---- instance of this block (ranges are sorted by blk_begin)
@@ -247,15 +251,18 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
     const int z1 = min(z0 + I.zc, nz);
     const int64_t plane = (int64_t)nx * ny;
     const int eff = parity ^ I.par_off;
-    const T *__restrict__ Uin = (const T *)I.vel[eff][0];
-    const T *__restrict__ Vin = (const T *)I.vel[eff][1];
-    const T *__restrict__ Win = (const T *)I.vel[eff][2];
-    const T *__restrict__ Pin = (const T *)I.pres[eff];
-    T *__restrict__ Uout = (T *)I.vel[eff ^ 1][0];
-    T *__restrict__ Vout = (T *)I.vel[eff ^ 1][1];
-    T *__restrict__ Wout = (T *)I.vel[eff ^ 1][2];
-    T *__restrict__ Pout = (T *)I.pres[eff ^ 1];
-    const uint32_t *__restrict__ codes = I.codes;
+    // Pointers read from the instance table are generic; placing them in the
+    // global address space gives global (not flat) memory instructions, which
+    // do not share a wait counter with LDS traffic.
+    const T GLOBAL_AS *__restrict__ Uin = (const T GLOBAL_AS *)I.vel[eff][0];
+    const T GLOBAL_AS *__restrict__ Vin = (const T GLOBAL_AS *)I.vel[eff][1];
+    const T GLOBAL_AS *__restrict__ Win = (const T GLOBAL_AS *)I.vel[eff][2];
+    const T GLOBAL_AS *__restrict__ Pin = (const T GLOBAL_AS *)I.pres[eff];
+    T GLOBAL_AS *__restrict__ Uout = (T GLOBAL_AS *)I.vel[eff ^ 1][0];
+    T GLOBAL_AS *__restrict__ Vout = (T GLOBAL_AS *)I.vel[eff ^ 1][1];
+    T GLOBAL_AS *__restrict__ Wout = (T GLOBAL_AS *)I.vel[eff ^ 1][2];
+    T GLOBAL_AS *__restrict__ Pout = (T GLOBAL_AS *)I.pres[eff ^ 1];
+    const uint32_t GLOBAL_AS *__restrict__ codes = (const uint32_t GLOBAL_AS *)I.codes;
     const T nu = (T)I.nu, dt = (T)I.dt, c2dt = (T)I.c2dt;
     const T gu = I.axis == 0 ? (T)I.drive : T(0);
     const T gv = I.axis == 1 ? (T)I.drive : T(0);
@@ -272,49 +279,31 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
     const int own = wrap_int(gy, ny) * nx + wrap_int(gx, nx);
     const int cl = (ty + 2) * PX + (tx + 2);  // own position in the padded plane
 
-    // ---- halo positions of the padded plane (up to two per thread)
-    int hoff[2], hlds[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int h = tid + j * NT;
-        hoff[j] = -1;
-        hlds[j] = 0;
-        if (h < NHALO) {
-            int px, py;
-            if (h < 2 * PX) {
-                py = h / PX;
-                px = h % PX;
-            } else if (h < 4 * PX) {
-                const int hh = h - 2 * PX;
-                py = PY - 2 + hh / PX;
-                px = hh % PX;
-            } else {
-                const int hh = h - 4 * PX;
-                py = 2 + hh / 4;
-                const int c = hh % 4;
-                px = c < 2 ? c : PX - 4 + c;
-            }
-            hlds[j] = py * PX + px;
-            hoff[j] = wrap_int(y0 - 2 + py, ny) * nx + wrap_int(x0 - 2 + px, nx);
-        }
-    }
-    // ---- halo pressure cell: left column (x0-1, y0..) then bottom row (x0-1.., y0-1)
-    int hp_off = -1, hp_q = 0, hp_c = 0;
-    if (tid < NHP) {
-        int qx, qy;
-        if (tid < TY) {
-            qx = 0;
-            qy = 1 + tid;
+    // ---- halo position of this thread in the padded plane (ring of width 2)
+    const bool has_halo = tid < NHALO;
+    int hoff = 0, hlds = 0;
+    bool has_ph = false;  // the -x column / -y row that p^{n-1} needs
+    if (has_halo) {
+        int px, py;
+        if (tid < 2 * PX) {
+            py = tid / PX;
+            px = tid % PX;
+        } else if (tid < 4 * PX) {
+            const int hh = tid - 2 * PX;
+            py = PY - 2 + hh / PX;
+            px = hh % PX;
         } else {
-            qx = tid - TY;
-            qy = 0;
+            const int hh = tid - 4 * PX;
+            py = 2 + hh / 4;
+            const int c = hh % 4;
+            px = c < 2 ? c : PX - 4 + c;
         }
-        hp_q = qy * (TX + 1) + qx;
-        hp_c = (qy + 1) * PX + (qx + 1);
-        hp_off = wrap_int(y0 - 1 + qy, ny) * nx + wrap_int(x0 - 1 + qx, nx);
+        hlds = py * PX + px;
+        hoff = wrap_int(y0 - 2 + py, ny) * nx + wrap_int(x0 - 2 + px, nx);
+        has_ph = (px == 1 && py >= 2 && py <= TY + 1) || (py == 1 && px >= 2 && px <= TX + 1);
     }
 
-    // ---- register windows, primed for the prologue plane zz = z0 - 1
+    // ---- prime the registers for the prologue plane zz = z0 - 1
     T Uw[5], Vw[5], Ww[3];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
@@ -324,138 +313,149 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
     }
 #pragma unroll
     for (int j = 0; j < 3; ++j) Ww[j] = Win[(int64_t)wrap_int(z0 - 2 + j, nz) * plane + own];
-    int zcur = wrap_int(z0 - 1, nz);  // plane zz
-    int zA = wrap_int(z0 + 2, nz);    // zz + 3: next u, v window plane
-    int zB = wrap_int(z0 + 1, nz);    // zz + 2: next w window plane
-    int zC = wrap_int(z0, nz);        // zz + 1: next pressure / code plane
-    T pold = Pin[(int64_t)zcur * plane + own];
+    int zP = wrap_int(z0 - 1, nz);  // plane zz
+    T pold = Pin[(int64_t)zP * plane + own];
     uint32_t code = 0;
+    T hU = T(0), hV = T(0), hW = T(0), hP = T(0);
+    if (has_halo) {
+        hU = Uin[(int64_t)zP * plane + hoff];
+        hV = Vin[(int64_t)zP * plane + hoff];
+        hW = Win[(int64_t)wrap_int(z0, nz) * plane + hoff];
+        if (has_ph) hP = Pin[(int64_t)zP * plane + hoff];
+    }
+    int zcur = zP;                  // zz
+    int z1p = wrap_int(z0, nz);     // zz + 1
+    int z2p = wrap_int(z0 + 1, nz); // zz + 2
+    int z3p = wrap_int(z0 + 2, nz); // zz + 3
+    int slot = 0;                   // u, v, p slot of plane zz
+    int wc = 0, wn = 1;             // w slots of planes zz and zz + 1
     T pn_prev = T(0);
 
     double acc[kNumSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    __syncthreads();  // coefficient table
 
     for (int zz = z0 - 1; zz < z1; ++zz) {
         const bool body = zz >= z0;
-        const int64_t pbase = (int64_t)zcur * plane;
-        // prefetch the next window planes (used after this plane)
-        const bool more = zz + 1 < z1;
-        T nU = T(0), nV = T(0), nW = T(0), nP = T(0);
-        uint32_t nC = 0;
-        if (more) {
-            nU = Uin[(int64_t)zA * plane + own];
-            nV = Vin[(int64_t)zA * plane + own];
-            nW = Win[(int64_t)zB * plane + own];
-            nP = Pin[(int64_t)zC * plane + own];
-            nC = codes[(int64_t)zC * plane + own];
+        T *const su = sh.u[slot];
+        T *const sv = sh.v[slot];
+        T *const sp = sh.p[slot];
+        T *const swc = sh.w[wc];
+        T *const swn = sh.w[wn];
+
+        // ---- stage plane zz (u, v, p) and plane zz + 1 (w)
+        su[cl] = Uw[2];
+        sv[cl] = Vw[2];
+        sp[cl] = pold;
+        swn[cl] = Ww[2];
+        if (has_halo) {
+            su[hlds] = hU;
+            sv[hlds] = hV;
+            swn[hlds] = hW;
+            if (has_ph) sp[hlds] = hP;
         }
 
-        // ---- stage plane zz of u, v, w
-        sh.u[cl] = Uw[2];
-        sh.v[cl] = Vw[2];
-        sh.w[cl] = Ww[1];
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-            if (hoff[j] >= 0) {
-                sh.u[hlds[j]] = Uin[pbase + hoff[j]];
-                sh.v[hlds[j]] = Vin[pbase + hoff[j]];
-                sh.w[hlds[j]] = Win[pbase + hoff[j]];
-            }
-        T hp_w1 = T(0), hp_pold = T(0);
-        if (hp_off >= 0) {
-            hp_w1 = Win[(int64_t)zC * plane + hp_off];
-            hp_pold = Pin[pbase + hp_off];
+        // ---- loads for the next plane (planes wrap, so every address is valid)
+        const T nU = Uin[(int64_t)z3p * plane + own];
+        const T nV = Vin[(int64_t)z3p * plane + own];
+        const T nW = Win[(int64_t)z2p * plane + own];
+        const T nP = Pin[(int64_t)z1p * plane + own];
+        const uint32_t nC = codes[(int64_t)z1p * plane + own];
+        T nhU = T(0), nhV = T(0), nhW = T(0), nhP = T(0);
+        if (has_halo) {
+            nhU = Uin[(int64_t)z1p * plane + hoff];
+            nhV = Vin[(int64_t)z1p * plane + hoff];
+            nhW = Win[(int64_t)z2p * plane + hoff];
+            if (has_ph) nhP = Pin[(int64_t)z1p * plane + hoff];
         }
         __syncthreads();
 
-        // ---- pressure p^n of plane zz (tile and -x/-y halo)
-        T dvg = divergence(Uw[2], sh.u[cl + 1], Vw[2], sh.v[cl + PX], Ww[1], Ww[2]);
+        // ---- p^n of the own cell
+        const T dvg = divergence(Uw[2], su[cl + 1], Vw[2], sv[cl + PX], Ww[1], Ww[2]);
         const T pn = skip ? pold : fma(-c2dt, dvg, pold);
-        sh.p[(ty + 1) * (TX + 1) + (tx + 1)] = pn;
-        if (hp_off >= 0) {
-            const T hd = divergence(sh.u[hp_c], sh.u[hp_c + 1], sh.v[hp_c], sh.v[hp_c + PX], sh.w[hp_c], hp_w1);
-            sh.p[hp_q] = skip ? hp_pold : fma(-c2dt, hd, hp_pold);
-        }
-        if (body && active) {
-            Pout[pbase + own] = pn;
-            if (reduce) {
-                const double nd = (double)(nu * dvg);
-                acc[1] += nd * nd;
-            }
-        }
-        __syncthreads();
 
-        // ---- velocity v^{n+1} of plane zz
         if (body && active) {
-            const int pq = (ty + 1) * (TX + 1) + (tx + 1);
-            const T pc = sh.p[pq];
+            // p^n of the -x and -y neighbours, from the staged planes
+            const T dxm = divergence(su[cl - 1], Uw[2], sv[cl - 1], sv[cl - 1 + PX], swc[cl - 1], swn[cl - 1]);
+            const T pxm = skip ? sp[cl - 1] : fma(-c2dt, dxm, sp[cl - 1]);
+            const T dym = divergence(su[cl - PX], su[cl - PX + 1], sv[cl - PX], Vw[2], swc[cl - PX], swn[cl - PX]);
+            const T pym = skip ? sp[cl - PX] : fma(-c2dt, dym, sp[cl - PX]);
+            const int64_t o = (int64_t)zcur * plane + own;
+            Pout[o] = pn;
             // u: own axis x, across y (LDS) and z (registers)
             const uint32_t cu = code;
             const T u0 = Uw[2];
-            const T u_d2x = d2_own(sh.u[cl - 1], u0, sh.u[cl + 1]);
-            const T u_d2y = d2_perp(sh.tab[cu & 7], sh.u[cl - 2 * PX], sh.u[cl - PX], u0, sh.u[cl + PX],
-                                    sh.u[cl + 2 * PX]);
+            const T u_d2x = d2_own(su[cl - 1], u0, su[cl + 1]);
+            const T u_d2y = d2_perp(sh.tab[cu & 7], su[cl - 2 * PX], su[cl - PX], u0, su[cl + PX], su[cl + 2 * PX]);
             const T u_d2z = d2_perp(sh.tab[(cu >> 3) & 7], Uw[0], Uw[1], u0, Uw[3], Uw[4]);
-            const T Fu = momentum(u_d2x, u_d2y, u_d2z, pc, sh.p[pq - 1], nu, gu);
-            const bool su = (cu & kSolidBit) != 0;
-            Uout[pbase + own] = su ? T(0) : fma(dt, Fu, u0);
+            const T Fu = momentum(u_d2x, u_d2y, u_d2z, pn, pxm, nu, gu);
+            const bool su_ = (cu & kSolidBit) != 0;
+            Uout[o] = su_ ? T(0) : fma(dt, Fu, u0);
             // v: own axis y, across x (LDS) and z (registers)
             const uint32_t cv = code >> kCodeBits;
             const T v0 = Vw[2];
-            const T v_d2x = d2_perp(sh.tab[cv & 7], sh.v[cl - 2], sh.v[cl - 1], v0, sh.v[cl + 1], sh.v[cl + 2]);
-            const T v_d2y = d2_own(sh.v[cl - PX], v0, sh.v[cl + PX]);
+            const T v_d2x = d2_perp(sh.tab[cv & 7], sv[cl - 2], sv[cl - 1], v0, sv[cl + 1], sv[cl + 2]);
+            const T v_d2y = d2_own(sv[cl - PX], v0, sv[cl + PX]);
             const T v_d2z = d2_perp(sh.tab[(cv >> 3) & 7], Vw[0], Vw[1], v0, Vw[3], Vw[4]);
-            const T Fv = momentum(v_d2x, v_d2y, v_d2z, pc, sh.p[pq - (TX + 1)], nu, gv);
-            const bool sv = (cv & kSolidBit) != 0;
-            Vout[pbase + own] = sv ? T(0) : fma(dt, Fv, v0);
+            const T Fv = momentum(v_d2x, v_d2y, v_d2z, pn, pym, nu, gv);
+            const bool sv_ = (cv & kSolidBit) != 0;
+            Vout[o] = sv_ ? T(0) : fma(dt, Fv, v0);
             // w: own axis z (registers), across x and y (LDS)
             const uint32_t cw = code >> (2 * kCodeBits);
             const T w0 = Ww[1];
-            const T w_d2x = d2_perp(sh.tab[cw & 7], sh.w[cl - 2], sh.w[cl - 1], w0, sh.w[cl + 1], sh.w[cl + 2]);
-            const T w_d2y = d2_perp(sh.tab[(cw >> 3) & 7], sh.w[cl - 2 * PX], sh.w[cl - PX], w0,
-                                    sh.w[cl + PX], sh.w[cl + 2 * PX]);
+            const T w_d2x = d2_perp(sh.tab[cw & 7], swc[cl - 2], swc[cl - 1], w0, swc[cl + 1], swc[cl + 2]);
+            const T w_d2y = d2_perp(sh.tab[(cw >> 3) & 7], swc[cl - 2 * PX], swc[cl - PX], w0, swc[cl + PX],
+                                    swc[cl + 2 * PX]);
             const T w_d2z = d2_own(Ww[0], w0, Ww[2]);
             const T Fw = momentum(w_d2x, w_d2y, w_d2z, pn, pn_prev, nu, gw);
-            const bool sw = (cw & kSolidBit) != 0;
-            Wout[pbase + own] = sw ? T(0) : fma(dt, Fw, w0);
+            const bool sw_ = (cw & kSolidBit) != 0;
+            Wout[o] = sw_ ? T(0) : fma(dt, Fw, w0);
             if (reduce) {
-                const double fu = su ? 0.0 : (double)Fu, fv = sv ? 0.0 : (double)Fv,
-                             fw = sw ? 0.0 : (double)Fw;
+                const double fu = su_ ? 0.0 : (double)Fu, fv = sv_ ? 0.0 : (double)Fv,
+                             fw = sw_ ? 0.0 : (double)Fw;
                 acc[0] += fu * fu + fv * fv + fw * fw;
+                const double nd = (double)(nu * dvg);
+                acc[1] += nd * nd;
                 acc[2] += (double)u0;
                 acc[3] += (double)v0;
                 acc[4] += (double)w0;
             }
         }
-        __syncthreads();
 
-        // ---- advance the windows
+        // ---- advance
         pn_prev = pn;
-        if (more) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                Uw[j] = Uw[j + 1];
-                Vw[j] = Vw[j + 1];
-            }
-            Uw[4] = nU;
-            Vw[4] = nV;
-            Ww[0] = Ww[1];
-            Ww[1] = Ww[2];
-            Ww[2] = nW;
-            pold = nP;
-            code = nC;
-            zcur = zC;
-            zC = zB;
-            zB = zA;
-            zA = (zA + 1 == nz) ? 0 : zA + 1;
+        for (int j = 0; j < 4; ++j) {
+            Uw[j] = Uw[j + 1];
+            Vw[j] = Vw[j + 1];
         }
+        Uw[4] = nU;
+        Vw[4] = nV;
+        Ww[0] = Ww[1];
+        Ww[1] = Ww[2];
+        Ww[2] = nW;
+        pold = nP;
+        code = nC;
+        hU = nhU;
+        hV = nhV;
+        hW = nhW;
+        hP = nhP;
+        zcur = z1p;
+        z1p = z2p;
+        z2p = z3p;
+        z3p = (z3p + 1 == nz) ? 0 : z3p + 1;
+        slot ^= 1;
+        wc = wn;
+        wn = (wn == 2) ? 0 : wn + 1;
     }
     if (reduce) block_sums(acc, sh.red, I.partials + lb * kNumSums);
 }
 
-bool fused_tile_supported(int tx, int ty)
+bool fused_tile_supported(int tx, int ty, int prec)
 {
-    return (tx == 64 && (ty == 4 || ty == 8 || ty == 16)) || (tx == 32 && (ty == 8 || ty == 16));
+    // one halo position per thread, and the LDS rings within 64 KiB
+    if (tx == 64 && ty == 8) return true;
+    if (tx == 32 && (ty == 8 || ty == 16)) return true;
+    if (tx == 64 && ty == 16) return prec == kF32;
+    return false;
 }
 
 template <typename T>
@@ -469,11 +469,12 @@ static hipError_t launch_fused_t(int tx, int ty, const InstDev *insts, int ninst
                            reduce);                                                                        \
         return hipGetLastError();                                                                          \
     }
-    PS_FUSED_CASE(64, 4)
     PS_FUSED_CASE(64, 8)
-    PS_FUSED_CASE(64, 16)
     PS_FUSED_CASE(32, 8)
     PS_FUSED_CASE(32, 16)
+    if constexpr (sizeof(T) == 4) {
+        PS_FUSED_CASE(64, 16)
+    }
 #undef PS_FUSED_CASE
     return hipErrorInvalidValue;
 }
@@ -482,6 +483,7 @@ hipError_t launch_fused(Prec prec, int tx, int ty, const InstDev *insts, int nin
                         int reduce, hipStream_t s)
 {
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (!fused_tile_supported(tx, ty, prec)) return hipErrorInvalidValue;
     return prec == kF64 ? launch_fused_t<double>(tx, ty, insts, ninst, nblocks, parity, reduce, s)
                         : launch_fused_t<float>(tx, ty, insts, ninst, nblocks, parity, reduce, s);
 }

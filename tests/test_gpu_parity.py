@@ -115,7 +115,8 @@ def test_iterate_fp64_against_oracle(ctx, name, count):
         assert np.abs(g - w).max() / scale <= 1e-12
 
 
-TILES = [(64, 8, 0), (64, 4, 3), (64, 16, 1), (32, 8, 5), (32, 16, 2), (64, 8, 64)]
+TILES = [(64, 8, 0), (64, 8, 3), (32, 16, 1), (32, 8, 5), (32, 16, 2), (64, 8, 64)]
+TILES_F32 = [(64, 16, 1), (64, 16, 0)]
 
 
 @pytest.mark.parametrize("name", ["spheres_70x13x11", "ragged_33x17x6", "thin_3x2x5", "extruded_16x16x1"])
@@ -126,7 +127,7 @@ def test_kernel_variants_bitwise(ctx, name, prec):
     mask = MASKS[name]()
     st = random_state(mask, 5)
     ref = gpu_iterate(ctx, mask, 1, st, 9, prec, kernel=ps.KERNEL_SIMPLE)
-    for tx, ty, zc in TILES:
+    for tx, ty, zc in TILES + (TILES_F32 if prec == ps.FP32 else []):
         got = gpu_iterate(ctx, mask, 1, st, 9, prec, kernel=ps.KERNEL_FUSED, tile_x=tx, tile_y=ty,
                           zchunk=zc)
         for g, r in zip(got, ref):
