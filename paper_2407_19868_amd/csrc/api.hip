@@ -208,10 +208,10 @@ struct TileCfg {
 int auto_zc(int nx, int ny, int nz, int tx, int ty)
 {
     const int64_t txy = (int64_t)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
-    // aim for >= 2048 workgroups (8 per CU) while keeping chunks long enough to
-    // amortise the 5-plane priming of the register window
-    int64_t zc = (int64_t)nz * txy / 2048;
-    zc = std::max<int64_t>(8, std::min<int64_t>(64, zc));
+    // aim for >= 512 workgroups (two 8-wave groups per CU) while keeping chunks
+    // long enough to amortise priming the z window (7 extra planes of u and v)
+    int64_t zc = (int64_t)nz * txy * tx * ty / (512LL * 512LL);
+    zc = std::max<int64_t>(16, std::min<int64_t>(64, zc));
     return (int)std::min<int64_t>(zc, nz);
 }
 
@@ -225,8 +225,9 @@ TileCfg pick_tiles(pm_ctx *ctx, const pm_params *prm, int nx, int ny, int nz, Pr
         c.ty = it->second[1];
         c.zc = it->second[2];
     } else {
+        // measured defaults on MI355X (256^3 packing): FP64 64x8, FP32 64x16
         c.tx = 64;
-        c.ty = 8;
+        c.ty = prec == kF64 ? 8 : 16;
         c.zc = 0;
     }
     if (prm->tile_x && prm->tile_y) {

@@ -207,8 +207,11 @@ hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream
 // its own cell and of its -x and -y neighbours (the pressure gradient of a
 // face reads the cell behind it), so pressures are never exchanged.  LDS
 // slots rotate (u, v, p over 2 planes, w over 3), which leaves one barrier
-// per plane, and every global load -- own column and halo -- is issued one
-// plane before it is needed.
+// per plane, and every global load -- own column and halo -- is issued two
+// planes before it is needed (HBM latency spans more than one plane's work).
+
+// MI355X: 8 XCDs of 32 CUs; workgroup i of a dispatch goes to XCD i mod 8.
+constexpr int kNumXcd = 8;
 
 template <typename T, int TX, int TY>
 struct FusedShared {
@@ -231,8 +234,14 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
     static_assert(NHALO <= NT, "one halo position per thread");
     __shared__ FusedShared<T, TX, TY> sh;
 
+    // ---- XCD-aware order: workgroups are dispatched round-robin over the
+    // XCDs, each with its own L2.  Give each XCD a contiguous run of tiles so
+    // that the halo reads of neighbouring tiles hit the L2 that loaded them.
+    const int64_t nbk = gridDim.x, xcd = blockIdx.x % kNumXcd, kx = blockIdx.x / kNumXcd;
+    const int64_t q = nbk / kNumXcd, rem = nbk % kNumXcd;
+    const int64_t b = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + kx;
+
     // ---- instance of this block (ranges are sorted by blk_begin)
-    const int64_t b = blockIdx.x;
     int lo = 0, hi = ninst - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -303,7 +312,8 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
         has_ph = (px == 1 && py >= 2 && py <= TY + 1) || (py == 1 && px >= 2 && px <= TX + 1);
     }
 
-    // ---- prime the registers for the prologue plane zz = z0 - 1
+    // ---- prime the registers for the prologue plane zz = z0 - 1 and the
+    // loads of plane z0 (loads run two planes ahead of their use)
     T Uw[5], Vw[5], Ww[3];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
@@ -313,20 +323,33 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
     }
 #pragma unroll
     for (int j = 0; j < 3; ++j) Ww[j] = Win[(int64_t)wrap_int(z0 - 2 + j, nz) * plane + own];
-    int zP = wrap_int(z0 - 1, nz);  // plane zz
-    T pold = Pin[(int64_t)zP * plane + own];
+    int zcur = wrap_int(z0 - 1, nz);  // zz
+    int z1p = wrap_int(z0, nz);       // zz + 1
+    int z2p = wrap_int(z0 + 1, nz);   // zz + 2
+    int z3p = wrap_int(z0 + 2, nz);   // zz + 3
+    int z4p = wrap_int(z0 + 3, nz);   // zz + 4
+    T pold = Pin[(int64_t)zcur * plane + own];
     uint32_t code = 0;
     T hU = T(0), hV = T(0), hW = T(0), hP = T(0);
     if (has_halo) {
-        hU = Uin[(int64_t)zP * plane + hoff];
-        hV = Vin[(int64_t)zP * plane + hoff];
-        hW = Win[(int64_t)wrap_int(z0, nz) * plane + hoff];
-        if (has_ph) hP = Pin[(int64_t)zP * plane + hoff];
+        hU = Uin[(int64_t)zcur * plane + hoff];
+        hV = Vin[(int64_t)zcur * plane + hoff];
+        hW = Win[(int64_t)z1p * plane + hoff];
+        if (has_ph) hP = Pin[(int64_t)zcur * plane + hoff];
     }
-    int zcur = zP;                  // zz
-    int z1p = wrap_int(z0, nz);     // zz + 1
-    int z2p = wrap_int(z0 + 1, nz); // zz + 2
-    int z3p = wrap_int(z0 + 2, nz); // zz + 3
+    // values for iteration zz + 1
+    T aU = Uin[(int64_t)z3p * plane + own];
+    T aV = Vin[(int64_t)z3p * plane + own];
+    T aW = Win[(int64_t)z2p * plane + own];
+    T aP = Pin[(int64_t)z1p * plane + own];
+    uint32_t aC = codes[(int64_t)z1p * plane + own];
+    T ahU = T(0), ahV = T(0), ahW = T(0), ahP = T(0);
+    if (has_halo) {
+        ahU = Uin[(int64_t)z1p * plane + hoff];
+        ahV = Vin[(int64_t)z1p * plane + hoff];
+        ahW = Win[(int64_t)z2p * plane + hoff];
+        if (has_ph) ahP = Pin[(int64_t)z1p * plane + hoff];
+    }
     int slot = 0;                   // u, v, p slot of plane zz
     int wc = 0, wn = 1;             // w slots of planes zz and zz + 1
     T pn_prev = T(0);
@@ -353,18 +376,24 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
             if (has_ph) sp[hlds] = hP;
         }
 
-        // ---- loads for the next plane (planes wrap, so every address is valid)
-        const T nU = Uin[(int64_t)z3p * plane + own];
-        const T nV = Vin[(int64_t)z3p * plane + own];
-        const T nW = Win[(int64_t)z2p * plane + own];
-        const T nP = Pin[(int64_t)z1p * plane + own];
-        const uint32_t nC = codes[(int64_t)z1p * plane + own];
-        T nhU = T(0), nhV = T(0), nhW = T(0), nhP = T(0);
-        if (has_halo) {
-            nhU = Uin[(int64_t)z1p * plane + hoff];
-            nhV = Vin[(int64_t)z1p * plane + hoff];
-            nhW = Win[(int64_t)z2p * plane + hoff];
-            if (has_ph) nhP = Pin[(int64_t)z1p * plane + hoff];
+        // ---- loads for iteration zz + 2 (planes wrap, so every address is
+        // valid); the last two iterations of the chunk need none
+        const bool ahead = zz + 2 < z1;
+        T bU = T(0), bV = T(0), bW = T(0), bP = T(0);
+        uint32_t bC = 0;
+        if (ahead) {
+            bU = Uin[(int64_t)z4p * plane + own];
+            bV = Vin[(int64_t)z4p * plane + own];
+            bW = Win[(int64_t)z3p * plane + own];
+            bP = Pin[(int64_t)z2p * plane + own];
+            bC = codes[(int64_t)z2p * plane + own];
+        }
+        T bhU = T(0), bhV = T(0), bhW = T(0), bhP = T(0);
+        if (has_halo && ahead) {
+            bhU = Uin[(int64_t)z2p * plane + hoff];
+            bhV = Vin[(int64_t)z2p * plane + hoff];
+            bhW = Win[(int64_t)z3p * plane + hoff];
+            if (has_ph) bhP = Pin[(int64_t)z2p * plane + hoff];
         }
         __syncthreads();
 
@@ -427,21 +456,31 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
             Uw[j] = Uw[j + 1];
             Vw[j] = Vw[j + 1];
         }
-        Uw[4] = nU;
-        Vw[4] = nV;
+        Uw[4] = aU;
+        Vw[4] = aV;
         Ww[0] = Ww[1];
         Ww[1] = Ww[2];
-        Ww[2] = nW;
-        pold = nP;
-        code = nC;
-        hU = nhU;
-        hV = nhV;
-        hW = nhW;
-        hP = nhP;
+        Ww[2] = aW;
+        pold = aP;
+        code = aC;
+        hU = ahU;
+        hV = ahV;
+        hW = ahW;
+        hP = ahP;
+        aU = bU;
+        aV = bV;
+        aW = bW;
+        aP = bP;
+        aC = bC;
+        ahU = bhU;
+        ahV = bhV;
+        ahW = bhW;
+        ahP = bhP;
         zcur = z1p;
         z1p = z2p;
         z2p = z3p;
-        z3p = (z3p + 1 == nz) ? 0 : z3p + 1;
+        z3p = z4p;
+        z4p = (z4p + 1 == nz) ? 0 : z4p + 1;
         slot ^= 1;
         wc = wn;
         wn = (wn == 2) ? 0 : wn + 1;
