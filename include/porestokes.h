@@ -91,7 +91,13 @@ typedef struct {
     int32_t tile_x;     /* fused-kernel tile override (0 = auto): 32 or 64           */
     int32_t tile_y;     /* fused-kernel tile override (0 = auto): 4, 8 or 16         */
     int32_t zchunk;     /* planes per workgroup along z (0 = auto)                   */
-    int32_t reserved[4];
+    int32_t graphs;     /* 1: each block of check_every sweeps (plus its reduction
+                           and copy-back) is captured once as a HIP graph and
+                           replayed; 0: launched directly.      default 1            */
+    int32_t autotune;   /* 1: before solving, time the fused-kernel decompositions
+                           on each new (shape, precision) and keep the fastest in
+                           the context (see pm_autotune).        default 0            */
+    int32_t reserved[2];
 } pm_params;
 
 /* Residual history: one record per check.  Host arrays of length cap owned by
@@ -219,6 +225,19 @@ typedef struct {
  */
 pm_status pm_solve_batch(pm_ctx *ctx, void *stream, pm_instance *inst, int32_t n,
                          const pm_params *params);
+
+/*
+ * Autotuner: time the fused sweep for each supported decomposition (tile
+ * 64x8, 32x8, 32x16, and 64x16 in FP32; z-chunks 16..128 planes) on this mask
+ * and precision (PM_FP64 or PM_FP32), from rest, and keep the fastest for the
+ * shape (nx, ny, nz) in the context; later solves of that shape use it unless
+ * params fix a tile.  If the environment variable PORESTOKES_TUNE_CACHE names
+ * a file, choices are loaded from it at pm_create and written back here (a
+ * flat JSON object "NXxNYxNZ:f64" -> [tile_x, tile_y, zchunk]).  best (host,
+ * 3 ints, may be NULL) receives the choice.  Synchronises the stream.
+ */
+pm_status pm_autotune(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny,
+                      int64_t nz, int precision, int32_t best[3]);
 
 /* Timing of the sweep kernels of the last pm_iterate / pm_solve / pm_tensor /
  * pm_solve_batch call on a context, measured with HIP events recorded on the

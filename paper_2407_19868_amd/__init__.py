@@ -29,7 +29,7 @@ KERNEL_AUTO, KERNEL_FUSED, KERNEL_SIMPLE = 0, 1, 2
 # Every symbol declared in include/porestokes.h.
 EXPORTS = ("pm_params_default", "pm_status_string", "pm_create", "pm_destroy", "pm_last_error",
            "pm_mem_used", "pm_preprocess", "pm_face_codes", "pm_iterate", "pm_residual", "pm_solve",
-           "pm_tensor", "pm_solve_batch", "pm_last_stats")
+           "pm_tensor", "pm_solve_batch", "pm_last_stats", "pm_autotune")
 
 
 class PmParams(ctypes.Structure):
@@ -48,7 +48,9 @@ class PmParams(ctypes.Structure):
         ("tile_x", ctypes.c_int32),
         ("tile_y", ctypes.c_int32),
         ("zchunk", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("graphs", ctypes.c_int32),
+        ("autotune", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -142,6 +144,8 @@ def load_library(path: str = LIB_PATH):
     lib.pm_solve_batch.restype = i32
     lib.pm_last_stats.argtypes = [vp, ctypes.POINTER(PmStats)]
     lib.pm_last_stats.restype = i32
+    lib.pm_autotune.argtypes = [vp, vp, vp, i64, i64, i64, i32, vp]
+    lib.pm_autotune.restype = i32
     _lib = lib
     return lib
 
@@ -255,6 +259,14 @@ class Context:
 
     def mem_used(self) -> int:
         return int(self._lib.pm_mem_used(self._h))
+
+    def autotune(self, mask, precision: int = FP64) -> tuple:
+        """Time the fused-kernel decompositions on this mask; returns (tile_x, tile_y, zchunk)."""
+        m, nx, ny, nz = _mask3(mask)
+        best = np.zeros(3, dtype=np.int32)
+        self._check(self._lib.pm_autotune(self._h, _stream(), m.data_ptr(), nx, ny, nz, precision,
+                                          best.ctypes.data))
+        return tuple(int(v) for v in best)
 
     def last_stats(self) -> dict:
         """Sweep-kernel timing of the last call (HIP events on the call's stream)."""

@@ -190,6 +190,7 @@ pm_status check_params(pm_ctx *ctx, const pm_params *p)
             return fail(ctx, PM_ERR_ARG, "unsupported tile %dx%d for this precision", p->tile_x, p->tile_y);
     }
     if (p->zchunk < 0) return fail(ctx, PM_ERR_ARG, "zchunk must be >= 0");
+    if (p->graphs != 0 && p->graphs != 1) return fail(ctx, PM_ERR_ARG, "graphs must be 0 or 1");
     return PM_OK;
 }
 
@@ -197,6 +198,61 @@ pm_status set_device(pm_ctx *ctx)
 {
     PM_HIP(hipSetDevice(ctx->dev));
     return PM_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+
+std::string tune_key(int nx, int ny, int nz, Prec prec)
+{
+    return std::to_string(nx) + "x" + std::to_string(ny) + "x" + std::to_string(nz) + (prec == kF64 ? ":f64" : ":f32");
+}
+
+// Tuning cache file: a flat JSON object {"NXxNYxNZ:f64": [tx, ty, zc], ...}.
+void load_tune_cache(pm_ctx *ctx)
+{
+    const char *path = std::getenv("PORESTOKES_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+    std::fclose(f);
+    size_t pos = 0;
+    for (;;) {
+        size_t k0 = text.find('"', pos);
+        if (k0 == std::string::npos) break;
+        size_t k1 = text.find('"', k0 + 1);
+        size_t b0 = text.find('[', k1);
+        size_t b1 = text.find(']', b0);
+        if (k1 == std::string::npos || b0 == std::string::npos || b1 == std::string::npos) break;
+        int tx = 0, ty = 0, zc = 0;
+        if (std::sscanf(text.c_str() + b0, "[%d , %d , %d]", &tx, &ty, &zc) == 3 ||
+            std::sscanf(text.c_str() + b0, "[%d,%d,%d]", &tx, &ty, &zc) == 3)
+            ctx->tune[text.substr(k0 + 1, k1 - k0 - 1)] = {tx, ty, zc};
+        pos = b1 + 1;
+    }
+}
+
+void save_tune_cache(const pm_ctx *ctx)
+{
+    const char *path = std::getenv("PORESTOKES_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{");
+    bool first = true;
+    for (const auto &kv : ctx->tune) {
+        if (kv.second.size() != 3) continue;
+        std::fprintf(f, "%s\n  \"%s\": [%d, %d, %d]", first ? "" : ",", kv.first.c_str(), kv.second[0],
+                     kv.second[1], kv.second[2]);
+        first = false;
+    }
+    std::fprintf(f, "\n}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
 }
 
 // ------------------------------------------------------------------ tiles
@@ -218,8 +274,7 @@ int auto_zc(int nx, int ny, int nz, int tx, int ty)
 TileCfg pick_tiles(pm_ctx *ctx, const pm_params *prm, int nx, int ny, int nz, Prec prec)
 {
     TileCfg c;
-    auto it = ctx->tune.find(std::to_string(nx) + "x" + std::to_string(ny) + "x" + std::to_string(nz) +
-                             (prec == kF64 ? ":f64" : ":f32"));
+    auto it = ctx->tune.find(tune_key(nx, ny, nz, prec));
     if (it != ctx->tune.end() && it->second.size() == 3) {
         c.tx = it->second[0];
         c.ty = it->second[1];
@@ -260,8 +315,9 @@ struct Inst {
     void *internal = nullptr;
     int64_t local_n = 0, sweeps = 0;
     double rmin = INFINITY, qprev = -1.0;
-    int stall = 0;
+    int stall = 0, plateau_hits = 0;
     double r_last = INFINITY;
+    std::vector<double> rphase;  // residuals at the checks of the current phase
     bool active = false, needs_start = false;
     pm_status status = PM_OK;
     double kcol[3] = {0, 0, 0};
@@ -278,6 +334,36 @@ int64_t blocks_of(const Inst &in)
 
 size_t elem(Prec p) { return p == kF64 ? sizeof(double) : sizeof(float); }
 
+// Device-table entry of an instance (sweep n reads set n & 1 when par_off = 0 and parity = n & 1).
+InstDev make_dev(const Inst &in, const pm_params *prm, int64_t blk_begin, bool skip)
+{
+    InstDev d;
+    d.nx = in.nx;
+    d.ny = in.ny;
+    d.nz = in.nz;
+    d.axis = in.axis;
+    d.tiles_x = (in.nx + in.tile.tx - 1) / in.tile.tx;
+    d.tiles_y = (in.ny + in.tile.ty - 1) / in.tile.ty;
+    d.tiles_z = (in.nz + in.tile.zc - 1) / in.tile.zc;
+    d.zc = in.tile.zc;
+    d.blk_begin = blk_begin;
+    d.nblocks = in.nblocks;
+    d.codes = in.codes;
+    for (int s = 0; s < 2; ++s)
+        for (int f = 0; f < 3; ++f) d.vel[s][f] = in.set[s][f];
+    d.pres[0] = in.set[0][3];
+    d.pres[1] = in.set[1][3];
+    d.partials = in.partials;
+    d.nu = 1.0 / prm->re;
+    d.dt = prm->dt;
+    d.c2dt = prm->c2 * prm->dt;
+    d.drive = prm->drive;
+    d.par_off = skip ? 0 : (int)((in.local_n + 1) & 1);
+    d.skip = skip ? 1 : 0;
+    return d;
+}
+
+
 struct Engine {
     pm_ctx *ctx;
     hipStream_t stream;
@@ -292,8 +378,21 @@ struct Engine {
     std::vector<InstDev> h_tab;
     std::vector<PartialRef> h_refs;
 
+    // Captured sweep blocks, keyed by the launch sequence they replay.  A
+    // graph bakes in grid sizes and table pointers, not the table contents,
+    // so it stays valid while the same groups sweep; it is rebuilt when the
+    // set of active instances changes.
+    std::map<std::string, hipGraphExec_t> graphs;
+    hipStream_t cap_stream = nullptr;
+
     Engine(pm_ctx *c, hipStream_t s, const pm_params *p, std::vector<Inst> &i)
         : ctx(c), stream(s), prm(p), inst(i), scratch(c) {}
+
+    ~Engine()
+    {
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
 
     pm_status prepare()
     {
@@ -415,33 +514,7 @@ struct Engine {
         return PM_OK;
     }
 
-    InstDev dev_of(const Inst &in, int64_t blk_begin, bool skip) const
-    {
-        InstDev d;
-        d.nx = in.nx;
-        d.ny = in.ny;
-        d.nz = in.nz;
-        d.axis = in.axis;
-        d.tiles_x = (in.nx + in.tile.tx - 1) / in.tile.tx;
-        d.tiles_y = (in.ny + in.tile.ty - 1) / in.tile.ty;
-        d.tiles_z = (in.nz + in.tile.zc - 1) / in.tile.zc;
-        d.zc = in.tile.zc;
-        d.blk_begin = blk_begin;
-        d.nblocks = in.nblocks;
-        d.codes = in.codes;
-        for (int s = 0; s < 2; ++s)
-            for (int f = 0; f < 3; ++f) d.vel[s][f] = in.set[s][f];
-        d.pres[0] = in.set[0][3];
-        d.pres[1] = in.set[1][3];
-        d.partials = in.partials;
-        d.nu = 1.0 / prm->re;
-        d.dt = prm->dt;
-        d.c2dt = prm->c2 * prm->dt;
-        d.drive = prm->drive;
-        d.par_off = skip ? 0 : (int)((in.local_n + 1) & 1);
-        d.skip = skip ? 1 : 0;
-        return d;
-    }
+    InstDev dev_of(const Inst &in, int64_t blk_begin, bool skip) const { return make_dev(in, prm, blk_begin, skip); }
 
     // Launch `steps` fused sweeps for the selected instances (reduce on the
     // last) and bring their sums to ctx->h_sums in selection order.
@@ -477,23 +550,63 @@ struct Engine {
                               stream));
         int64_t vox = 0;
         for (int i : order) vox += inst[i].N;
-        PM_TRY(stats_mark(ctx, stream, true));
-        for (int j = 0; j < steps; ++j)
+        PM_TRY(ensure_events(ctx));
+        // the sequence: event, `steps` sweeps of every group (reduce on the
+        // last), event, final reduction, copy of the sums to pinned memory
+        auto enqueue = [&](hipStream_t st) -> pm_status {
+            PM_HIP(hipEventRecord(ctx->ev[0], st));
+            for (int j = 0; j < steps; ++j)
+                for (const Group &g : groups)
+                    PM_HIP(launch_fused(g.prec, g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1,
+                                        j == steps - 1 ? 1 : 0, st));
+            PM_HIP(hipEventRecord(ctx->ev[1], st));
+            PM_HIP(launch_reduce_partials(d_refs, (int)order.size(), d_sums, st));
+            PM_HIP(hipMemcpyAsync(ctx->h_sums, d_sums, order.size() * kNumSums * sizeof(double),
+                                  hipMemcpyDeviceToHost, st));
+            return PM_OK;
+        };
+        if (prm->graphs && !skip) {
+            std::string key = std::to_string(steps);
             for (const Group &g : groups)
-                PM_HIP(launch_fused(g.prec, g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1,
-                                    j == steps - 1 ? 1 : 0, stream));
-        PM_TRY(stats_mark(ctx, stream, false, (int64_t)steps * (int64_t)groups.size(), vox * steps));
+                key += "|" + std::to_string(g.prec) + ":" + std::to_string(g.tx) + "x" + std::to_string(g.ty) +
+                       ":" + std::to_string(g.first) + ":" + std::to_string(g.count) + ":" +
+                       std::to_string(g.blocks);
+            key += "|" + std::to_string(order.size());
+            auto it = graphs.find(key);
+            if (it == graphs.end()) {
+                if (!cap_stream) PM_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+                PM_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+                pm_status es = enqueue(cap_stream);
+                hipGraph_t g = nullptr;
+                hipError_t ee = hipStreamEndCapture(cap_stream, &g);
+                if (es != PM_OK) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return es;
+                }
+                PM_HIP(ee);
+                hipGraphExec_t ex = nullptr;
+                hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                PM_HIP(ei);
+                it = graphs.emplace(key, ex).first;
+            }
+            PM_HIP(hipGraphLaunch(it->second, stream));
+        } else {
+            PM_TRY(enqueue(stream));
+        }
+        PM_HIP(hipStreamSynchronize(stream));
         {
+            float ms = 0.f;
+            PM_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+            ctx->stats.sweep_ms += ms;
+            ctx->stats.sweep_launches += (int64_t)steps * (int64_t)groups.size();
+            ctx->stats.voxel_updates += vox * steps;
             const Inst &last = inst[order.back()];
             ctx->stats.tile_x = last.tile.tx;
             ctx->stats.tile_y = last.tile.ty;
             ctx->stats.zchunk = last.tile.zc;
             ctx->stats.precision = last.prec == kF64 ? PM_FP64 : PM_FP32;
         }
-        PM_HIP(launch_reduce_partials(d_refs, (int)order.size(), d_sums, stream));
-        PM_HIP(hipMemcpyAsync(ctx->h_sums, d_sums, order.size() * kNumSums * sizeof(double),
-                              hipMemcpyDeviceToHost, stream));
-        PM_HIP(hipStreamSynchronize(stream));
         // h_sums rows follow `order`; remap to `sel` positions
         sums_of.assign(inst.size(), nullptr);
         for (size_t r = 0; r < order.size(); ++r) sums_of[order[r]] = ctx->h_sums + r * kNumSums;
@@ -560,7 +673,31 @@ struct Engine {
         in.needs_start = true;
         in.rmin = INFINITY;
         in.stall = 0;
+        in.plateau_hits = 0;
+        in.rphase.clear();
         return PM_OK;
+    }
+
+    // FP32 rounding floor reached?  With r_n ~ r_inf + C rho^n, Aitken's
+    // extrapolation of three residuals K checks apart estimates r_inf; the
+    // iterate is at its floor once most of r is that limit (or r stopped
+    // falling).  Multi-rate decay can fool one estimate, so two consecutive
+    // hits are required.
+    bool at_fp32_floor(Inst &in) const
+    {
+        const std::vector<double> &h = in.rphase;
+        const size_t K = 5, n = h.size();
+        if (n < 2 * K + 1) return false;
+        const double a = h[n - 1 - 2 * K], b = h[n - 1 - K], c = h[n - 1];
+        bool hit;
+        if (!(b < a) || !(c < b)) {
+            hit = true;  // no progress over K checks
+        } else {
+            const double d1 = b - a, d2 = c - b, den = d2 - d1;
+            hit = den > 0 && (c - d2 * d2 / den) > 0.8 * c;
+        }
+        in.plateau_hits = hit ? in.plateau_hits + 1 : 0;
+        return in.plateau_hits >= 2;
     }
 
     // Convergence bookkeeping after a check of instance `in` with sums s.
@@ -572,6 +709,7 @@ struct Engine {
         in.qprev = qn;
         record(in, s, r, eps);
         in.r_last = r;
+        in.rphase.push_back(r);
         if (!std::isfinite(r) || r > 1e3 * in.rmin) {
             in.status = PM_DIVERGED;
             return finalize(in);
@@ -584,16 +722,16 @@ struct Engine {
         }
         const bool met = prm->stop_rule == 0 ? r < prm->tol : eps < prm->tol;
         const bool fp32_phase = in.prec == kF32;
+        const bool floor = fp32_phase && (in.stall >= 5 || at_fp32_floor(in));
         if (in.dc && fp32_phase) {
-            // hand over to FP64 once the FP32 iterate reaches the switch level,
-            // meets tol, or stops improving (its rounding floor)
-            const double sw = std::max(prm->tol, dc_switch());
-            if (met || r < sw || in.stall >= 5) return promote(in);
+            // hand over to FP64 once the FP32 iterate meets the stop rule (FP64
+            // confirms it) or sits at its rounding floor
+            if (met || floor) return promote(in);
         } else if (met) {
             in.status = PM_OK;
             return finalize(in);
         }
-        if (!in.dc && fp32_phase && in.stall >= 8) {
+        if (!in.dc && floor) {
             in.status = PM_NOT_CONVERGED;  // FP32 rounding floor above tol
             return finalize(in);
         }
@@ -603,8 +741,6 @@ struct Engine {
         }
         return PM_OK;
     }
-
-    double dc_switch() const { return 1e-6; }
 
     pm_status run()
     {
@@ -643,6 +779,92 @@ struct Engine {
         return PM_OK;
     }
 };
+
+// Time every supported decomposition of the fused sweep on one shape and
+// precision (from rest, on scratch fields) and keep the fastest.
+pm_status autotune_shape(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx, int ny, int nz, Prec prec,
+                         TileCfg *best_out)
+{
+    const int64_t N = (int64_t)nx * ny * nz;
+    Scratch scratch(ctx);
+    void *codes = nullptr, *fields = nullptr, *tab = nullptr, *part = nullptr;
+    PM_TRY(scratch.get((size_t)N * sizeof(uint32_t), &codes));
+    PM_TRY(scratch.get(8 * (size_t)N * elem(prec), &fields));
+    PM_TRY(scratch.get(2 * sizeof(InstDev), &tab));
+    PM_HIP(launch_face_codes(mask, nx, ny, nz, (uint32_t *)codes, s));
+    PM_HIP(hipMemsetAsync(fields, 0, 4 * (size_t)N * elem(prec), s));
+    const int tiles[4][2] = {{64, 8}, {32, 8}, {32, 16}, {64, 16}};
+    const int zcs[4] = {16, 32, 64, 128};
+    std::vector<TileCfg> cands;
+    for (auto &t : tiles) {
+        if (!fused_tile_supported(t[0], t[1], prec)) continue;
+        int last = -1;
+        for (int zc : zcs) {
+            const int z = std::min(zc, nz);
+            if (z == last) continue;
+            last = z;
+            TileCfg c;
+            c.tx = t[0];
+            c.ty = t[1];
+            c.zc = z;
+            cands.push_back(c);
+        }
+    }
+    int64_t maxb = 0;
+    for (const TileCfg &c : cands) {
+        Inst in;
+        in.nx = nx;
+        in.ny = ny;
+        in.nz = nz;
+        in.tile = c;
+        maxb = std::max(maxb, blocks_of(in));
+    }
+    PM_TRY(scratch.get((size_t)maxb * kNumSums * sizeof(double), &part));
+    pm_params prm;
+    pm_params_default(&prm);
+    // timed sweeps per candidate: ~2e9 voxel updates, at least 3
+    const int reps = (int)std::max<int64_t>(3, std::min<int64_t>(20, (int64_t)2000000000 / std::max<int64_t>(N, 1)));
+    PM_TRY(ensure_events(ctx));
+    float best_ms = INFINITY;
+    TileCfg best = cands.front();
+    for (const TileCfg &c : cands) {
+        Inst in;
+        in.nx = nx;
+        in.ny = ny;
+        in.nz = nz;
+        in.N = N;
+        in.codes = (uint32_t *)codes;
+        in.prec = prec;
+        for (int k = 0; k < 4; ++k) {
+            in.set[0][k] = (char *)fields + (size_t)k * N * elem(prec);
+            in.set[1][k] = (char *)fields + (size_t)(4 + k) * N * elem(prec);
+        }
+        in.tile = c;
+        in.nblocks = blocks_of(in);
+        in.partials = (double *)part;
+        InstDev d[2] = {make_dev(in, &prm, 0, true), make_dev(in, &prm, 0, false)};
+        d[1].par_off = 1;
+        PM_HIP(hipMemcpyAsync(tab, d, sizeof d, hipMemcpyHostToDevice, s));
+        InstDev *dt = (InstDev *)tab;
+        PM_HIP(launch_fused(prec, c.tx, c.ty, dt, 1, in.nblocks, 0, 0, s));
+        PM_HIP(launch_fused(prec, c.tx, c.ty, dt + 1, 1, in.nblocks, 0, 0, s));
+        PM_HIP(hipEventRecord(ctx->ev[0], s));
+        for (int r = 0; r < reps; ++r)
+            PM_HIP(launch_fused(prec, c.tx, c.ty, dt + 1, 1, in.nblocks, (r + 1) & 1, 0, s));
+        PM_HIP(hipEventRecord(ctx->ev[1], s));
+        PM_HIP(hipEventSynchronize(ctx->ev[1]));
+        float ms = 0.f;
+        PM_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    ctx->tune[tune_key(nx, ny, nz, prec)] = {best.tx, best.ty, best.zc};
+    save_tune_cache(ctx);
+    if (best_out) *best_out = best;
+    return PM_OK;
+}
 
 int severity(pm_status s)
 {
@@ -694,6 +916,7 @@ void pm_params_default(pm_params *p)
     p->stop_rule = 0;
     p->warm_start = 0;
     p->kernel = PM_KERNEL_AUTO;
+    p->graphs = 1;
 }
 
 const char *pm_status_string(pm_status s)
@@ -723,6 +946,7 @@ pm_status pm_create(int hip_device, size_t mem_cap_bytes, pm_ctx **out)
     if (!ctx) return PM_ERR_OOM;
     ctx->dev = hip_device;
     ctx->cap = mem_cap_bytes;
+    load_tune_cache(ctx);
     if (hipSetDevice(hip_device) != hipSuccess) {
         delete ctx;
         return PM_ERR_DEVICE;
@@ -899,6 +1123,27 @@ pm_status pm_residual(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx
     return PM_OK;
 }
 
+pm_status pm_autotune(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz,
+                      int precision, int32_t best[3])
+{
+    if (!ctx) return PM_ERR_ARG;
+    ctx->err.clear();
+    if (!mask) return fail(ctx, PM_ERR_ARG, "mask is NULL");
+    PM_TRY(check_dims(ctx, nx, ny, nz));
+    if (precision != PM_FP64 && precision != PM_FP32)
+        return fail(ctx, PM_ERR_ARG, "pm_autotune takes PM_FP64 or PM_FP32");
+    PM_TRY(set_device(ctx));
+    TileCfg c;
+    PM_TRY(autotune_shape(ctx, (hipStream_t)stream, mask, (int)nx, (int)ny, (int)nz,
+                          precision == PM_FP64 ? kF64 : kF32, &c));
+    if (best) {
+        best[0] = c.tx;
+        best[1] = c.ty;
+        best[2] = c.zc;
+    }
+    return PM_OK;
+}
+
 pm_status pm_solve_batch(pm_ctx *ctx, void *stream, pm_instance *insts, int32_t n, const pm_params *params)
 {
     if (!ctx) return PM_ERR_ARG;
@@ -934,6 +1179,15 @@ pm_status pm_solve_batch(pm_ctx *ctx, void *stream, pm_instance *insts, int32_t 
         if (in.hist) in.hist->n = 0;
     }
     PM_TRY(set_device(ctx));
+    if (params->autotune && !(params->tile_x && params->tile_y) && params->zchunk == 0) {
+        std::vector<Prec> precs;
+        if (params->precision != PM_FP64) precs.push_back(kF32);
+        if (params->precision != PM_FP32) precs.push_back(kF64);
+        for (const Inst &in : list)
+            for (Prec pr : precs)
+                if (!ctx->tune.count(tune_key(in.nx, in.ny, in.nz, pr)))
+                    PM_TRY(autotune_shape(ctx, (hipStream_t)stream, in.mask, in.nx, in.ny, in.nz, pr, nullptr));
+    }
     stats_begin(ctx);
     pm_status rs;
     {

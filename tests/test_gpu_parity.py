@@ -268,3 +268,76 @@ def test_memory_cap(ctx):
     with ps.Context(0, mem_cap=4096) as small:
         with pytest.raises(ps.PorestokesError, match="ERR_OOM"):
             small.solve(m, 0)
+
+
+# ------------------------------------------------------------ graphs, tuning, precision forms
+
+def test_graph_replay_equals_direct_launches(ctx):
+    mask = synth.spheres(20, 18, 16, 2.0, 3.0, 0.5, 71)
+    m = ps.to_device(mask)
+    a = ctx.solve(m, 1, ps.params(graphs=1))
+    b = ctx.solve(m, 1, ps.params(graphs=0))
+    assert a.status == b.status == "OK"
+    assert a.sweeps == b.sweeps
+    assert np.array_equal(a.kcol, b.kcol)
+    assert np.array_equal(a.hist_r, b.hist_r)
+    for fa, fb in zip(a.fields, b.fields):
+        assert torch.equal(fa, fb)
+
+
+@pytest.mark.parametrize("prec", [ps.FP64, ps.FP32])
+def test_autotune_choice_is_supported_and_exact(prec):
+    mask = synth.spheres(40, 36, 30, 2.0, 3.5, 0.5, 72)
+    m = ps.to_device(mask)
+    with ps.Context(0) as c:
+        ref = c.solve(m, 0, ps.params(precision=prec, max_sweeps=300))
+        best = c.autotune(m, prec)
+        assert best[0] in (32, 64) and best[1] in (8, 16) and 1 <= best[2] <= 30
+        tuned = c.solve(m, 0, ps.params(precision=prec, max_sweeps=300))
+        assert c.last_stats()["tile_x"] == best[0] and c.last_stats()["zchunk"] == best[2]
+        assert np.array_equal(ref.kcol, tuned.kcol)
+        assert np.array_equal(ref.hist_r, tuned.hist_r)
+
+
+def test_solve_with_autotune_flag(ctx):
+    mask = synth.spheres(24, 20, 18, 2.0, 3.0, 0.5, 73)
+    m = ps.to_device(mask)
+    g = ctx.solve(m, 2, ps.params(autotune=1))
+    o = oracle.solve(mask, 2, oracle.params())
+    assert g.status == o.status == "OK" and g.sweeps == o.sweeps
+    assert normwise(g.kcol, o.kcol) <= 1e-10
+
+
+def test_fp32_dc_hands_over_to_fp64(ctx):
+    """The FP32 phase stops at its rounding floor (or at tol) and the FP64 phase
+    restarts from the promoted state: its first record repeats the sweep count."""
+    mask = synth.test_grid(102)
+    g = ctx.solve(ps.to_device(mask), 1, ps.params(precision=ps.FP32_DC, tol=1e-10))
+    assert g.status == "OK"
+    dup = np.nonzero(np.diff(g.hist_sweep) == 0)[0]
+    assert dup.size == 1  # one hand-over: FP32 record, then FP64 record at the same sweep
+    assert g.hist_r[-1] < 1e-10
+    o = oracle.solve(mask, 1, oracle.params(tol=1e-10))
+    assert normwise(g.kcol, o.kcol) <= 1e-7
+
+
+def test_fp32_form_reaches_floor_with_k_within_1e5(ctx):
+    mask = synth.test_grid(100)
+    g = ctx.solve(ps.to_device(mask), 0, ps.params(precision=ps.FP32))
+    o = oracle.solve(mask, 0, oracle.params())
+    assert g.status in ("OK", "NOT_CONVERGED")
+    assert normwise(g.kcol, o.kcol) <= 1e-5
+    assert g.fields[0].dtype == torch.float32
+
+
+def test_batch_clogged_instance_only_changes_its_status(ctx):
+    open_ = synth.spheres(20, 16, 12, 2.0, 2.5, 0.5, 74)
+    clogged = open_.copy()
+    clogged[:, :, 7] = 1  # a solid wall normal to x blocks flow along x
+    probs = [(ps.to_device(open_), 0), (ps.to_device(clogged), 0), (ps.to_device(open_), 1)]
+    st, res = ctx.solve_batch(probs, ps.params())
+    assert [r["status"] for r in res][0] == "OK" and res[2]["status"] == "OK"
+    assert res[1]["status"] in ("OK", "NO_FLOW")
+    assert abs(res[1]["kcol"][0]) < 1e-12
+    single = ctx.solve(probs[0][0], 0)
+    assert np.array_equal(res[0]["kcol"], single.kcol)
