@@ -45,10 +45,11 @@ def cpu_baseline(mask, seconds: float):
     """Oracle sweeps of one load axis from rest, count calibrated to ~`seconds`."""
     import oracle
     nz, ny, nx = mask.shape
+    oracle.run_sweeps(mask, 0, 1)  # first touch of the buffers
     t0 = time.perf_counter()
-    oracle.run_sweeps(mask, 0, 1)
-    t1 = time.perf_counter() - t0
-    n = max(1, int(round(seconds / max(t1, 1e-6))))
+    oracle.run_sweeps(mask, 0, 3)
+    t3 = (time.perf_counter() - t0) / 3.0
+    n = max(1, int(round(seconds / max(t3, 1e-6))))
     t0 = time.perf_counter()
     oracle.run_sweeps(mask, 0, n)
     dt = time.perf_counter() - t0
@@ -64,7 +65,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sweeps-per-step", type=int, default=500)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="form of the main line; the other form is reported beside it")
     ap.add_argument("--size", type=int, default=256, help="cube edge (256 = the named workload)")
     ap.add_argument("--no-tensor", action="store_true", help="skip the time-to-tensor solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -94,55 +96,59 @@ def main() -> int:
         mask_np = synth.spheres(n, n, n, 6.0, 10.0, 0.35, 2)
     mask = ps.to_device(mask_np)
     ctx = ps.Context(0)
-    prec = ps.FP64 if args.precision == "fp64" else ps.FP32
     tile = {}
     if args.tile:
         tx, ty, zc = (int(v) for v in args.tile.split("x"))
         tile = {"tile_x": tx, "tile_y": ty, "zchunk": zc}
-    prm = ps.params(precision=prec, max_sweeps=args.sweeps_per_step, **tile)
     N = mask_np.size
 
-    def step():
-        r = ctx.tensor(mask, prm)
-        if r.status not in ("NOT_CONVERGED", "OK"):
-            raise RuntimeError(f"tensor step failed: {r.status} {ctx.last_error()}")
-        return r, ctx.last_stats()
+    def measure(form: str):
+        """Warmup + timed steps of one precision form -> (value, roofline, ms_per_step, tile)."""
+        prec = ps.FP64 if form == "fp64" else ps.FP32
+        prm = ps.params(precision=prec, max_sweeps=args.sweeps_per_step, **tile)
 
-    for i in range(args.warmup):
-        step()
-        log(f"[bench] warmup {i} done")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sweeps = 0
-    launches = 0
-    sweep_ms = 0.0
-    vox_launch = 0
-    last_stats = None
-    for i in range(args.steps):
-        r, st = step()
-        sweeps += int(r.sweeps.sum())
-        launches += st["sweep_launches"]
-        sweep_ms += st["sweep_ms"]
-        vox_launch += st["voxel_updates"]
-        last_stats = st
-        log(f"[bench] step {i}: {st['total_ms']:.1f} ms, {st['sweep_launches']} launches, "
-            f"{st['sweep_ms']:.1f} ms in sweeps")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    voxel_updates = N * sweeps
-    value = voxel_updates / wall / 1e9
-    avg_launch_s = sweep_ms / 1e3 / max(launches, 1)
-    bytes_per_launch = BYTES_PER_VOXEL[args.precision] * (vox_launch / max(launches, 1))
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        def step():
+            r = ctx.tensor(mask, prm)
+            if r.status not in ("NOT_CONVERGED", "OK"):
+                raise RuntimeError(f"tensor step failed: {r.status} {ctx.last_error()}")
+            return r, ctx.last_stats()
+
+        for i in range(args.warmup):
+            step()
+            log(f"[bench] {form} warmup {i} done")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sweeps = launches = vox_launch = 0
+        sweep_ms = 0.0
+        st = None
+        for i in range(args.steps):
+            r, st = step()
+            sweeps += int(r.sweeps.sum())
+            launches += st["sweep_launches"]
+            sweep_ms += st["sweep_ms"]
+            vox_launch += st["voxel_updates"]
+            log(f"[bench] {form} step {i}: {st['total_ms']:.1f} ms, {st['sweep_launches']} launches, "
+                f"{st['sweep_ms']:.1f} ms in sweep blocks")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        value = N * sweeps / wall / 1e9
+        avg_launch_s = sweep_ms / 1e3 / max(launches, 1)
+        bpv = BYTES_PER_VOXEL[form]
+        achieved = bpv * (vox_launch / max(launches, 1)) / avg_launch_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"k_fused<{'double' if prec == ps.FP64 else 'float'},"
-                          f"{last_stats['tile_x']},{last_stats['tile_y']}>",
+                "kernel": f"k_fused<{'double' if prec == ps.FP64 else 'float'},{st['tile_x']},{st['tile_y']}>",
                 "avg_launch_us": round(avg_launch_s * 1e6, 2),
                 "voxels_per_launch": int(vox_launch / max(launches, 1)),
-                "bytes_per_voxel": BYTES_PER_VOXEL[args.precision]}
-    log(f"[bench] {value:.2f} GVox/s whole-step, kernel {achieved:.0f} GB/s "
-        f"({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)")
+                "bytes_per_voxel": bpv}
+        log(f"[bench] {form}: {value:.2f} GVox/s whole-step, kernel {achieved:.0f} GB/s "
+            f"({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)")
+        return value, roof, 1e3 * wall / max(args.steps, 1), [st["tile_x"], st["tile_y"], st["zchunk"]]
+
+    main_form = args.precision
+    other_form = "fp32" if main_form == "fp64" else "fp64"
+    value, roofline, ms_step, tile_used = measure(main_form)
+    o_value, o_roof, o_ms, o_tile = measure(other_form)
 
     out = {
         "metric": "GVoxel-updates/s per sweep (% HBM roofline); time-to-k-tensor FP32 vs FP64",
@@ -151,20 +157,22 @@ def main() -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * wall / max(args.steps, 1), 2),
+        "ms_per_step": round(ms_step, 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == ps.FP64 else "f32",
+        "dtype": "f64" if main_form == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"overlapping spheres {n}^3, radius U[6,10], porosity 0.35, seed 2; "
                                f"3 load axes batched; {args.sweeps_per_step} sweeps per step, "
                                f"residual check every 100",
                    "grid": [n, n, n], "load_axes": 3, "sweeps_per_step": args.sweeps_per_step,
-                   "tile": [last_stats["tile_x"], last_stats["tile_y"], last_stats["zchunk"]],
-                   "parallelism": "single GPU"},
+                   "tile": tile_used, "parallelism": "single GPU"},
         "roofline": roofline,
-        "single_sweep_roofline_gvox": round(HBM_PEAK_GBS / BYTES_PER_VOXEL[args.precision], 1),
+        "single_sweep_roofline_gvox": round(HBM_PEAK_GBS / BYTES_PER_VOXEL[main_form], 1),
+        other_form: {"value": round(o_value, 3), "unit": "GVoxel-updates/s", "ms_per_step": round(o_ms, 2),
+                     "roofline": o_roof, "tile": o_tile,
+                     "single_sweep_roofline_gvox": round(HBM_PEAK_GBS / BYTES_PER_VOXEL[other_form], 1)},
     }
 
     if not args.no_tensor:

@@ -241,7 +241,9 @@ pm_status pm_autotune(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx
 
 /* Timing of the sweep kernels of the last pm_iterate / pm_solve / pm_tensor /
  * pm_solve_batch call on a context, measured with HIP events recorded on the
- * call's stream around each run of consecutive sweep launches. */
+ * call's stream around each run of consecutive sweep launches (in a solve: a
+ * block of check_every sweeps plus its final reduction and 40-byte copy-back
+ * per instance). */
 typedef struct {
     int64_t sweep_launches;  /* sweep-kernel launches                                  */
     int64_t voxel_updates;   /* voxels swept, summed over launches (all instances)     */

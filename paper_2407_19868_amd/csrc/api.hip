@@ -551,15 +551,14 @@ struct Engine {
         int64_t vox = 0;
         for (int i : order) vox += inst[i].N;
         PM_TRY(ensure_events(ctx));
-        // the sequence: event, `steps` sweeps of every group (reduce on the
-        // last), event, final reduction, copy of the sums to pinned memory
+        // the sequence: `steps` sweeps of every group (reduce on the last),
+        // final reduction, copy of the sums to pinned memory.  Timing events
+        // bracket it on the caller's stream (for a graph: around the launch).
         auto enqueue = [&](hipStream_t st) -> pm_status {
-            PM_HIP(hipEventRecord(ctx->ev[0], st));
             for (int j = 0; j < steps; ++j)
                 for (const Group &g : groups)
                     PM_HIP(launch_fused(g.prec, g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1,
                                         j == steps - 1 ? 1 : 0, st));
-            PM_HIP(hipEventRecord(ctx->ev[1], st));
             PM_HIP(launch_reduce_partials(d_refs, (int)order.size(), d_sums, st));
             PM_HIP(hipMemcpyAsync(ctx->h_sums, d_sums, order.size() * kNumSums * sizeof(double),
                                   hipMemcpyDeviceToHost, st));
@@ -590,9 +589,13 @@ struct Engine {
                 PM_HIP(ei);
                 it = graphs.emplace(key, ex).first;
             }
+            PM_HIP(hipEventRecord(ctx->ev[0], stream));
             PM_HIP(hipGraphLaunch(it->second, stream));
+            PM_HIP(hipEventRecord(ctx->ev[1], stream));
         } else {
+            PM_HIP(hipEventRecord(ctx->ev[0], stream));
             PM_TRY(enqueue(stream));
+            PM_HIP(hipEventRecord(ctx->ev[1], stream));
         }
         PM_HIP(hipStreamSynchronize(stream));
         {

@@ -295,8 +295,12 @@ def test_autotune_choice_is_supported_and_exact(prec):
         assert best[0] in (32, 64) and best[1] in (8, 16) and 1 <= best[2] <= 30
         tuned = c.solve(m, 0, ps.params(precision=prec, max_sweeps=300))
         assert c.last_stats()["tile_x"] == best[0] and c.last_stats()["zchunk"] == best[2]
-        assert np.array_equal(ref.kcol, tuned.kcol)
-        assert np.array_equal(ref.hist_r, tuned.hist_r)
+        # the iterate is bitwise identical; sums over another block decomposition
+        # differ by rounding of the summation order only
+        for fa, fb in zip(ref.fields, tuned.fields):
+            assert torch.equal(fa, fb)
+        assert np.allclose(ref.kcol, tuned.kcol, rtol=1e-13, atol=0)
+        assert np.allclose(ref.hist_r, tuned.hist_r, rtol=1e-12, atol=0)
 
 
 def test_solve_with_autotune_flag(ctx):
@@ -338,6 +342,6 @@ def test_batch_clogged_instance_only_changes_its_status(ctx):
     st, res = ctx.solve_batch(probs, ps.params())
     assert [r["status"] for r in res][0] == "OK" and res[2]["status"] == "OK"
     assert res[1]["status"] in ("OK", "NO_FLOW")
-    assert abs(res[1]["kcol"][0]) < 1e-12
+    assert abs(res[1]["kcol"][0]) < 1e-6 * res[0]["kcol"][0]
     single = ctx.solve(probs[0][0], 0)
     assert np.array_equal(res[0]["kcol"], single.kcol)
