@@ -209,6 +209,9 @@ hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream
 // slots rotate (u, v, p over 2 planes, w over 3), which leaves one barrier
 // per plane, and every global load -- own column and halo -- is issued two
 // planes before it is needed (HBM latency spans more than one plane's work).
+// Results and stencil codes are touched once per launch: their stores and
+// loads are non-temporal, leaving L2 to the planes that neighbouring tiles
+// read again as halo.
 
 // MI355X: 8 XCDs of 32 CUs; workgroup i of a dispatch goes to XCD i mod 8.
 constexpr int kNumXcd = 8;
@@ -342,7 +345,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
     T aV = Vin[(int64_t)z3p * plane + own];
     T aW = Win[(int64_t)z2p * plane + own];
     T aP = Pin[(int64_t)z1p * plane + own];
-    uint32_t aC = codes[(int64_t)z1p * plane + own];
+    uint32_t aC = __builtin_nontemporal_load(&codes[(int64_t)z1p * plane + own]);
     T ahU = T(0), ahV = T(0), ahW = T(0), ahP = T(0);
     if (has_halo) {
         ahU = Uin[(int64_t)z1p * plane + hoff];
@@ -386,7 +389,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
             bV = Vin[(int64_t)z4p * plane + own];
             bW = Win[(int64_t)z3p * plane + own];
             bP = Pin[(int64_t)z2p * plane + own];
-            bC = codes[(int64_t)z2p * plane + own];
+            bC = __builtin_nontemporal_load(&codes[(int64_t)z2p * plane + own]);
         }
         T bhU = T(0), bhV = T(0), bhW = T(0), bhP = T(0);
         if (has_halo && ahead) {
@@ -408,7 +411,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
             const T dym = divergence(su[cl - PX], su[cl - PX + 1], sv[cl - PX], Vw[2], swc[cl - PX], swn[cl - PX]);
             const T pym = skip ? sp[cl - PX] : fma(-c2dt, dym, sp[cl - PX]);
             const int64_t o = (int64_t)zcur * plane + own;
-            Pout[o] = pn;
+            __builtin_nontemporal_store(pn, &Pout[o]);
             // u: own axis x, across y (LDS) and z (registers)
             const uint32_t cu = code;
             const T u0 = Uw[2];
@@ -417,7 +420,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
             const T u_d2z = d2_perp(sh.tab[(cu >> 3) & 7], Uw[0], Uw[1], u0, Uw[3], Uw[4]);
             const T Fu = momentum(u_d2x, u_d2y, u_d2z, pn, pxm, nu, gu);
             const bool su_ = (cu & kSolidBit) != 0;
-            Uout[o] = su_ ? T(0) : fma(dt, Fu, u0);
+            __builtin_nontemporal_store(su_ ? T(0) : fma(dt, Fu, u0), &Uout[o]);
             // v: own axis y, across x (LDS) and z (registers)
             const uint32_t cv = code >> kCodeBits;
             const T v0 = Vw[2];
@@ -426,7 +429,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
             const T v_d2z = d2_perp(sh.tab[(cv >> 3) & 7], Vw[0], Vw[1], v0, Vw[3], Vw[4]);
             const T Fv = momentum(v_d2x, v_d2y, v_d2z, pn, pym, nu, gv);
             const bool sv_ = (cv & kSolidBit) != 0;
-            Vout[o] = sv_ ? T(0) : fma(dt, Fv, v0);
+            __builtin_nontemporal_store(sv_ ? T(0) : fma(dt, Fv, v0), &Vout[o]);
             // w: own axis z (registers), across x and y (LDS)
             const uint32_t cw = code >> (2 * kCodeBits);
             const T w0 = Ww[1];
@@ -436,7 +439,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
             const T w_d2z = d2_own(Ww[0], w0, Ww[2]);
             const T Fw = momentum(w_d2x, w_d2y, w_d2z, pn, pn_prev, nu, gw);
             const bool sw_ = (cw & kSolidBit) != 0;
-            Wout[o] = sw_ ? T(0) : fma(dt, Fw, w0);
+            __builtin_nontemporal_store(sw_ ? T(0) : fma(dt, Fw, w0), &Wout[o]);
             if (reduce) {
                 const double fu = su_ ? 0.0 : (double)Fu, fv = sv_ ? 0.0 : (double)Fv,
                              fw = sw_ ? 0.0 : (double)Fw;
@@ -490,11 +493,10 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
 
 bool fused_tile_supported(int tx, int ty, int prec)
 {
-    // one halo position per thread, and the LDS rings within 64 KiB
-    if (tx == 64 && ty == 8) return true;
-    if (tx == 32 && (ty == 8 || ty == 16)) return true;
-    if (tx == 64 && ty == 16) return prec == kF32;
-    return false;
+    // one halo position per thread; LDS rings within a workgroup's 160 KiB
+    // (64x16 in FP64 takes 98 KiB: one workgroup of 16 waves per CU)
+    (void)prec;
+    return (tx == 64 && (ty == 8 || ty == 16)) || (tx == 32 && (ty == 8 || ty == 16));
 }
 
 template <typename T>
@@ -509,11 +511,9 @@ static hipError_t launch_fused_t(int tx, int ty, const InstDev *insts, int ninst
         return hipGetLastError();                                                                          \
     }
     PS_FUSED_CASE(64, 8)
+    PS_FUSED_CASE(64, 16)
     PS_FUSED_CASE(32, 8)
     PS_FUSED_CASE(32, 16)
-    if constexpr (sizeof(T) == 4) {
-        PS_FUSED_CASE(64, 16)
-    }
 #undef PS_FUSED_CASE
     return hipErrorInvalidValue;
 }
