@@ -54,11 +54,12 @@ uint64_t synth_splitmix64(uint64_t state_in, uint64_t *state_out)
     return r;
 }
 
+/* Minimum-image displacement along a periodic axis of length n, for
+ * |d| < 3n/2 (every caller passes a difference of two coordinates in [0, n)). */
 static double min_image(double d, double n)
 {
-    d = fmod(d, n);
     if (d > 0.5 * n) d -= n;
-    if (d < -0.5 * n) d += n;
+    else if (d < -0.5 * n) d += n;
     return d;
 }
 
