@@ -119,7 +119,7 @@ def series_workload(args) -> dict:
                 "autotuned decomposition")
     masks = [ps.to_device(m) for m in states]
     probs = [(m, a) for m in masks for a in axes]
-    prm = ps.params(precision=ps.FP32_DC, max_sweeps=args.max_sweeps, autotune=1)
+    prm = ps.params(precision=ps.FP32_DC, max_sweeps=args.max_sweeps, autotune=1, progress=20)
     if args.workload == "foam":
         # tune outside the timed solve (one pass per distinct shape)
         for m in masks:

@@ -97,7 +97,10 @@ typedef struct {
     int32_t autotune;   /* 1: before solving, time the fused-kernel decompositions
                            on each new (shape, precision) and keep the fastest in
                            the context (see pm_autotune).        default 0            */
-    int32_t reserved[2];
+    int32_t progress;   /* > 0: every `progress` checks, print one line (sweeps,
+                           active instances, largest residual) to stderr; for
+                           long solves.                          default 0            */
+    int32_t reserved[1];
 } pm_params;
 
 /* Residual history: one record per check.  Host arrays of length cap owned by

@@ -50,7 +50,8 @@ class PmParams(ctypes.Structure):
         ("zchunk", ctypes.c_int32),
         ("graphs", ctypes.c_int32),
         ("autotune", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("progress", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 

@@ -191,6 +191,7 @@ pm_status check_params(pm_ctx *ctx, const pm_params *p)
     }
     if (p->zchunk < 0) return fail(ctx, PM_ERR_ARG, "zchunk must be >= 0");
     if (p->graphs != 0 && p->graphs != 1) return fail(ctx, PM_ERR_ARG, "graphs must be 0 or 1");
+    if (p->progress < 0) return fail(ctx, PM_ERR_ARG, "progress must be >= 0");
     return PM_OK;
 }
 
@@ -745,6 +746,8 @@ struct Engine {
         return PM_OK;
     }
 
+    int64_t nchecks = 0;
+
     pm_status run()
     {
         PM_TRY(prepare());
@@ -772,10 +775,19 @@ struct Engine {
             int64_t to_next = prm->check_every - (inst[actives[0]].sweeps % prm->check_every);
             const int steps = (int)std::max<int64_t>(1, std::min(to_next, remaining));
             PM_TRY(run_block(actives, steps, false));
+            double rworst = 0.0;
             for (int i : actives) {
                 inst[i].local_n += steps;
                 inst[i].sweeps += steps;
                 PM_TRY(check(inst[i], sums_of[i]));
+                rworst = std::max(rworst, inst[i].r_last);
+            }
+            if (prm->progress > 0 && (++nchecks % prm->progress) == 0) {
+                int nact = 0;
+                for (const Inst &in : inst) nact += in.active;
+                std::fprintf(stderr, "[porestokes] sweep %lld: %zu swept, %d still active, largest r %.3e\n",
+                             (long long)inst[actives[0]].sweeps, actives.size(), nact, rworst);
+                std::fflush(stderr);
             }
         }
         PM_HIP(hipStreamSynchronize(stream));
