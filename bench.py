@@ -37,8 +37,56 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_VOXEL = {"fp64": 64.375, "fp32": 32.375}
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_fused_spheres256.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_19868_amd", "csrc", f) for f in ("kernels.hip", "common.h")]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(form: str):
+    """HBM bytes per launch of the timed sweep kernel, from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the factor a
+    plain copy of known size gives) -- only while the kernel sources are the
+    ones the counters were taken on; otherwise None."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        line = line.strip()
+        if line.startswith("kernel_source_sha256:"):
+            vals["hash"] = line.split(":", 1)[1].strip()
+        elif line.startswith(f"traffic_bytes_per_launch_{form}:"):
+            vals["bytes"] = float(line.split(":", 1)[1].strip())
+    if vals.get("hash") != kernel_source_hash() or "bytes" not in vals:
+        return None
+    return vals["bytes"]
+
+
+def calibrate_copy() -> int:
+    """A plain device copy of known size (1 GiB read, 1 GiB written), for
+    scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    torch.cuda.set_device(0)
+    a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration copy: {a.numel() * 8} bytes read and written")
+    return 0
 
 
 def cpu_baseline(mask, seconds: float):
@@ -165,7 +213,11 @@ def main() -> int:
                          "batched series and the large single domain")
     ap.add_argument("--max-sweeps", type=int, default=200000,
                     help="sweep budget of the series solves (--workload precipitation/foam)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        return calibrate_copy()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -233,7 +285,8 @@ def main() -> int:
         bpv = BYTES_PER_VOXEL[form]
         achieved = bpv * (vox_launch / max(launches, 1)) / avg_launch_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(form),
+                "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": f"k_fused<{'double' if prec == ps.FP64 else 'float'},{st['tile_x']},{st['tile_y']}>",
                 "avg_launch_us": round(avg_launch_s * 1e6, 2),
                 "voxels_per_launch": int(vox_launch / max(launches, 1)),
