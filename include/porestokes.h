@@ -26,8 +26,9 @@
  *   Streams:    `stream` is a hipStream_t (NULL = default stream).  All device
  *               work of a call is ordered on it.  Calls that return numbers on
  *               the host (solve, tensor, batch, residual) synchronise that
- *               stream before returning; pm_preprocess, pm_face_codes and
- *               pm_iterate only enqueue work.
+ *               stream before returning; pm_preprocess and pm_face_codes only
+ *               enqueue work.  pm_iterate returns after its sweeps are done
+ *               (it releases its scratch buffers, which waits for the GPU).
  *   Errors:     every call returns pm_status.  Argument errors are detected
  *               before any device write.  The text of the last error is kept
  *               per context (pm_last_error).  No C++ exception crosses the ABI.
@@ -164,7 +165,8 @@ pm_status pm_face_codes(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t 
  * Run exactly `count` sweeps on the state (u, v, w, p) in place, load axis
  * `axis` (0 x, 1 y, 2 z).  Fields are device arrays of nx*ny*nz doubles
  * (params->precision PM_FP64) or floats (PM_FP32); PM_FP32_DC is rejected.
- * Faces touching solid are set to 0 first.  Enqueue only.
+ * Faces touching solid are set to 0 first.  Returns once the sweeps are
+ * complete (the call's scratch buffers are freed on return).
  */
 pm_status pm_iterate(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny,
                      int64_t nz, int axis, const pm_params *params, void *u, void *v, void *w,
@@ -231,7 +233,7 @@ pm_status pm_solve_batch(pm_ctx *ctx, void *stream, pm_instance *inst, int32_t n
 
 /*
  * Autotuner: time the fused sweep for each supported decomposition (tile
- * 64x8, 32x8, 32x16, and 64x16 in FP32; z-chunks 16..128 planes) on this mask
+ * 64x8, 32x8, 32x16 and 64x16; z-chunks 16..128 planes) on this mask
  * and precision (PM_FP64 or PM_FP32), from rest, and keep the fastest for the
  * shape (nx, ny, nz) in the context; later solves of that shape use it unless
  * params fix a tile.  If the environment variable PORESTOKES_TUNE_CACHE names
