@@ -227,9 +227,12 @@ struct FusedShared {
     double red[kNumSums * (TX * TY / 64)];
 };
 
-template <typename T, int TX, int TY>
+// RED: accumulate the residual and flux sums of the state (the launches at a
+// convergence check); the other launches carry no accumulators, which keeps
+// the FP64 64x16 variant within 128 VGPRs.
+template <typename T, int TX, int TY, bool RED>
 __global__ void __launch_bounds__(TX *TY)
-k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
+k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
 {
     constexpr int NT = TX * TY;
     constexpr int PX = TX + 4, PY = TY + 4;
@@ -440,7 +443,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
             const T Fw = momentum(w_d2x, w_d2y, w_d2z, pn, pn_prev, nu, gw);
             const bool sw_ = (cw & kSolidBit) != 0;
             __builtin_nontemporal_store(sw_ ? T(0) : fma(dt, Fw, w0), &Wout[o]);
-            if (reduce) {
+            if (RED) {
                 const double fu = su_ ? 0.0 : (double)Fu, fv = sv_ ? 0.0 : (double)Fv,
                              fw = sw_ ? 0.0 : (double)Fw;
                 acc[0] += fu * fu + fv * fv + fw * fw;
@@ -488,7 +491,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity, int reduce)
         wc = wn;
         wn = (wn == 2) ? 0 : wn + 1;
     }
-    if (reduce) block_sums(acc, sh.red, I.partials + lb * kNumSums);
+    if (RED) block_sums(acc, sh.red, I.partials + lb * kNumSums);
 }
 
 bool fused_tile_supported(int tx, int ty, int prec)
@@ -506,8 +509,12 @@ static hipError_t launch_fused_t(int tx, int ty, const InstDev *insts, int ninst
     const dim3 grid((unsigned)nblocks);
 #define PS_FUSED_CASE(TX_, TY_)                                                                             \
     if (tx == TX_ && ty == TY_) {                                                                          \
-        hipLaunchKernelGGL((k_fused<T, TX_, TY_>), grid, dim3(TX_ * TY_), 0, s, insts, ninst, parity,     \
-                           reduce);                                                                        \
+        if (reduce)                                                                                        \
+            hipLaunchKernelGGL((k_fused<T, TX_, TY_, true>), grid, dim3(TX_ * TY_), 0, s, insts, ninst,    \
+                               parity);                                                                    \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_fused<T, TX_, TY_, false>), grid, dim3(TX_ * TY_), 0, s, insts, ninst,   \
+                               parity);                                                                    \
         return hipGetLastError();                                                                          \
     }
     PS_FUSED_CASE(64, 8)
