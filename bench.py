@@ -344,6 +344,9 @@ def main() -> int:
         err = float(np.abs(ks["fp32_dc"] - ks["fp64"]).max() / np.abs(ks["fp64"]).max())
         tt["fp32_dc_vs_fp64_k_rel"] = err
         tt["speedup_fp32_dc"] = round(tt["fp64"]["seconds"] / tt["fp32_dc"]["seconds"], 3)
+        pa = ps.principal_axes(ks["fp64"], 0.05)
+        tt["principal_fp64"] = {"k_I_II_III": [float(f"{x:.8g}") for x in pa.lam], "class": pa.cls,
+                                "ratio_III_I": round(pa.ratio, 5), "rel_tol": 0.05}
         out["time_to_tensor"] = tt
 
     if not args.no_cpu:

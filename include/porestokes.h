@@ -261,6 +261,54 @@ typedef struct {
 /* Copy the statistics of the last call into *out (host). */
 pm_status pm_last_stats(const pm_ctx *ctx, pm_stats *out);
 
+/* ------------------------------------------------------------ principal axes
+ *
+ * Post-processing of a permeability tensor (host computation, no context, no
+ * GPU).  The principal permeabilities are the eigenvalues of the symmetric
+ * part k_sym = (k + k^T)/2 (the off-diagonals averaged as in App. C; §2
+ * eq. 3dK_eigen), the principal axes its unit eigenvectors, and the material
+ * class follows §2 from which of them are equal.
+ */
+typedef enum { PM_ISOTROPIC = 0, PM_TRANSVERSE = 1, PM_ORTHOTROPIC = 2 } pm_aniso_class;
+
+typedef struct {
+    double k_sym[9];   /* (k + k^T) / 2, row-major                                    */
+    double lambda[3];  /* principal permeabilities k_I <= k_II <= k_III                */
+    double R[9];       /* rotation tensor, row-major, R[k*3+i] = cos(e_k, e~_i): column
+                          i is the unit principal axis of lambda[i].  Columns 0 and 1
+                          have their largest-magnitude component positive, column 2 =
+                          column 0 x column 1 (det R = +1).  Axes of equal values are
+                          any orthonormal basis of their eigenspace.                 */
+    int32_t cls;       /* pm_aniso_class                                               */
+    int32_t distinct;  /* PM_TRANSVERSE: index (0..2) into lambda of the value that
+                          differs from the equal pair; -1 otherwise                    */
+    double ratio;      /* anisotropy ratio k_III / k_I (+inf when k_I <= 0)           */
+} pm_principal;
+
+/*
+ * k: host, 9 doubles, row-major k[i*3+j] = k_ij (as pm_tensor returns).
+ * Two principal values a, b count as equal when |a - b| <= rel_tol * max(|a|, |b|)
+ * (the paper's classes are exact equalities; rel_tol >= 0 sets the resolution).
+ * Class: PM_ISOTROPIC if k_I and k_III are equal; else PM_TRANSVERSE if k_I = k_II
+ * or k_II = k_III (both: the pair with the smaller relative gap); else
+ * PM_ORTHOTROPIC.  Errors: PM_ERR_ARG for NULL pointers, a negative or non-finite
+ * rel_tol or a non-finite entry of k.
+ */
+pm_status pm_principal_axes(const double k[9], double rel_tol, pm_principal *out);
+
+/*
+ * Principal directions within the plane of axes a and b (a != b, 0..2), the
+ * reduced two-dimensional evaluation of §6.4: with s = (k_ab + k_ba) / 2,
+ *   phi = atan2(2 s, k_bb - k_aa) / 2   (radians, in (-pi/2, pi/2]),
+ * so that sin(phi) e_a + cos(phi) e_b is the principal axis of the larger value
+ * lam[1] of the 2x2 block [[k_aa, s], [s, k_bb]]: the angle between e_b and that
+ * axis.  For k_bb > k_aa this is (1/2) arctan(2 s / (k_bb - k_aa)), §6.4's formula
+ * read with the difference of the diagonal entries in the denominator.  lam (host, 2): eigenvalues of the
+ * block, lam[0] <= lam[1].  Errors: PM_ERR_ARG for NULL pointers, bad or equal
+ * axes, non-finite entries.
+ */
+pm_status pm_plane_angle(const double k[9], int a, int b, double *phi, double lam[2]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,10 @@ KERNEL_AUTO, KERNEL_FUSED, KERNEL_SIMPLE = 0, 1, 2
 # Every symbol declared in include/porestokes.h.
 EXPORTS = ("pm_params_default", "pm_status_string", "pm_create", "pm_destroy", "pm_last_error",
            "pm_mem_used", "pm_preprocess", "pm_face_codes", "pm_iterate", "pm_residual", "pm_solve",
-           "pm_tensor", "pm_solve_batch", "pm_last_stats", "pm_autotune")
+           "pm_tensor", "pm_solve_batch", "pm_last_stats", "pm_autotune", "pm_principal_axes",
+           "pm_plane_angle")
+ISOTROPIC, TRANSVERSE, ORTHOTROPIC = 0, 1, 2
+CLASS_NAMES = {ISOTROPIC: "isotropic", TRANSVERSE: "transverse", ORTHOTROPIC: "orthotropic"}
 
 
 class PmParams(ctypes.Structure):
@@ -101,6 +104,17 @@ class PmStats(ctypes.Structure):
     ]
 
 
+class PmPrincipal(ctypes.Structure):
+    _fields_ = [
+        ("k_sym", ctypes.c_double * 9),
+        ("lam", ctypes.c_double * 3),
+        ("R", ctypes.c_double * 9),
+        ("cls", ctypes.c_int32),
+        ("distinct", ctypes.c_int32),
+        ("ratio", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -147,6 +161,12 @@ def load_library(path: str = LIB_PATH):
     lib.pm_last_stats.restype = i32
     lib.pm_autotune.argtypes = [vp, vp, vp, i64, i64, i64, i32, vp]
     lib.pm_autotune.restype = i32
+    d9 = ctypes.c_double * 9
+    lib.pm_principal_axes.argtypes = [ctypes.POINTER(d9), ctypes.c_double, ctypes.POINTER(PmPrincipal)]
+    lib.pm_principal_axes.restype = i32
+    lib.pm_plane_angle.argtypes = [ctypes.POINTER(d9), i32, i32, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double * 2)]
+    lib.pm_plane_angle.restype = i32
     _lib = lib
     return lib
 
@@ -396,6 +416,41 @@ class Context:
             out.append({"status": STATUS_NAMES[arr[i].status], "kcol": np.array(arr[i].k_col[:]),
                         "sweeps": int(arr[i].sweeps), "sweep": sw_[:hn].copy(), "r": r_[:hn].copy()})
         return STATUS_NAMES[st], out
+
+
+@dataclass
+class Principal:
+    k_sym: np.ndarray     # (k + k^T) / 2
+    lam: np.ndarray       # k_I <= k_II <= k_III
+    R: np.ndarray         # column i: principal axis of lam[i]
+    cls: str              # "isotropic" | "transverse" | "orthotropic"
+    distinct: int         # transverse: index of the differing value, else -1
+    ratio: float          # k_III / k_I
+
+
+def _k9(k) -> "ctypes.Array":
+    a = np.ascontiguousarray(np.asarray(k, dtype=np.float64).reshape(3, 3))
+    return (ctypes.c_double * 9)(*a.ravel().tolist())
+
+
+def principal_axes(k, rel_tol: float = 0.05) -> Principal:
+    """Principal permeabilities, axes and material class of a 3x3 tensor (pm_principal_axes)."""
+    out = PmPrincipal()
+    st = load_library().pm_principal_axes(ctypes.byref(_k9(k)), float(rel_tol), ctypes.byref(out))
+    if st != PM_OK:
+        raise PorestokesError(st, "pm_principal_axes: bad tensor or tolerance")
+    return Principal(np.array(out.k_sym[:]).reshape(3, 3), np.array(out.lam[:]), np.array(out.R[:]).reshape(3, 3),
+                     CLASS_NAMES[out.cls], int(out.distinct), float(out.ratio))
+
+
+def plane_angle(k, a: int, b: int) -> tuple[float, np.ndarray]:
+    """Principal angle (radians) and eigenvalues of the (a, b) block of a tensor (pm_plane_angle)."""
+    phi = ctypes.c_double()
+    lam = (ctypes.c_double * 2)()
+    st = load_library().pm_plane_angle(ctypes.byref(_k9(k)), int(a), int(b), ctypes.byref(phi), ctypes.byref(lam))
+    if st != PM_OK:
+        raise PorestokesError(st, "pm_plane_angle: bad tensor or axes")
+    return float(phi.value), np.array(lam[:])
 
 
 def to_device(mask: np.ndarray, device: int | str = "cuda") -> torch.Tensor:

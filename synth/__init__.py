@@ -62,6 +62,8 @@ def _load():
     lib.synth_foam.restype = None
     lib.synth_rescale_z.argtypes = [u8p, i64, i64, i64, i64, u8p]
     lib.synth_rescale_z.restype = None
+    lib.synth_ellipsoid.argtypes = [u8p, i64, i64, i64, f64, f64, f64, f64]
+    lib.synth_ellipsoid.restype = None
     lib.synth_splitmix64.argtypes = [u64, ctypes.POINTER(u64)]
     lib.synth_splitmix64.restype = u64
     _lib = lib
@@ -131,6 +133,18 @@ def rescale_z(mask: np.ndarray, nz_dst: int) -> np.ndarray:
 
 
 # ------------------------------------------------------------ named workloads
+
+def ellipsoid(nx: int, ny: int, nz: int, a: float, b: float, c: float, alpha_deg: float) -> np.ndarray:
+    """One ellipsoid (semi-axes a, b, c along e1, e2, e3) centred in the box, turned about e1."""
+    m = np.empty((nz, ny, nx), dtype=np.uint8)
+    _load().synth_ellipsoid(_ptr(m), nx, ny, nz, float(a), float(b), float(c), np.radians(alpha_deg))
+    return m
+
+
+def ellipsoid_100(alpha_deg: float) -> np.ndarray:
+    """The principal-direction benchmark: 100^3 box, semi-axes 35, 10, 35, turned by alpha about e1."""
+    return ellipsoid(100, 100, 100, 35.0, 10.0, 35.0, alpha_deg)
+
 
 def single_spheres_32() -> np.ndarray:
     """32^3 packing, radius 4, porosity 0.40, seed 1 (plain FP64 single solve)."""

@@ -339,3 +339,31 @@ void synth_rescale_z(const uint8_t *src, int64_t nx, int64_t ny, int64_t nz_src,
         memcpy(dst + z * P, src + zs * P, (size_t)P);
     }
 }
+
+/* ---------------------------------------------------------------- rotated ellipsoid */
+
+/*
+ * One solid ellipsoid centred in an nx x ny x nz periodic box, semi-axes a, b,
+ * c along e1, e2, e3 before it is turned about e1 by alpha (radians): the
+ * benchmark geometry of the principal-direction study (100^3 box, a = c = 35,
+ * b = 10).  A voxel is solid iff its centre p, relative to the box centre and
+ * turned back by -alpha, satisfies (x/a)^2 + (y'/b)^2 + (z'/c)^2 <= 1 with
+ * y' = cos(alpha) y + sin(alpha) z, z' = -sin(alpha) y + cos(alpha) z (minimum
+ * image, so a body wider than the box wraps around).
+ */
+void synth_ellipsoid(uint8_t *mask, int64_t nx, int64_t ny, int64_t nz, double a, double b, double c,
+                     double alpha)
+{
+    const double ca = cos(alpha), sa = sin(alpha);
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                const double x = min_image((double)i + 0.5 - 0.5 * (double)nx, (double)nx);
+                const double y = min_image((double)j + 0.5 - 0.5 * (double)ny, (double)ny);
+                const double z = min_image((double)k + 0.5 - 0.5 * (double)nz, (double)nz);
+                const double yr = ca * y + sa * z, zr = -sa * y + ca * z;
+                const double q = (x / a) * (x / a) + (yr / b) * (yr / b) + (zr / c) * (zr / c);
+                mask[(k * ny + j) * nx + i] = q <= 1.0;
+            }
+}

@@ -63,3 +63,20 @@ def test_foam_series_small():
     states = synth.foam_series(n=64, nseeds=12, radius=2.0, nstates=3, seed=4)
     assert [s.shape[0] for s in states] == synth.foam_strain_dims(64, 3)
     assert 0.5 < 1.0 - states[0].mean() < 0.99
+
+
+@pytest.mark.parametrize("n, axes", [(100, (35.0, 10.0, 35.0)), (50, (17.5, 5.0, 17.5))])
+@pytest.mark.parametrize("alpha", [0.0, 20.0, 40.0])
+def test_ellipsoid_volume_and_lattice_symmetries(n, axes, alpha):
+    """The turned ellipsoid: solid fraction near the analytic volume; turning
+    by a further 90 degrees equals rotating the voxel array; -alpha equals the
+    mirror image in y; at 45 degrees the body is symmetric under y <-> z.  These
+    are exact symmetries of the periodic cell that the flow tests rely on."""
+    a, b, c = axes
+    m = synth.ellipsoid(n, n, n, a, b, c, alpha)
+    assert m.mean() == pytest.approx(4.0 / 3.0 * np.pi * a * b * c / n ** 3, rel=0.02)
+    assert np.array_equal(synth.ellipsoid(n, n, n, a, b, c, alpha + 90.0), np.rot90(m, k=1, axes=(0, 1)))
+    assert np.array_equal(synth.ellipsoid(n, n, n, a, b, c, -alpha), m[:, ::-1, :])
+    m45 = synth.ellipsoid(n, n, n, a, b, c, 45.0)
+    assert np.array_equal(m45, m45.transpose(1, 0, 2))
+    assert np.array_equal(synth.ellipsoid_100(alpha), synth.ellipsoid(100, 100, 100, 35.0, 10.0, 35.0, alpha))
