@@ -167,7 +167,18 @@ def series_workload(args) -> dict:
                 "autotuned decomposition")
     masks = [ps.to_device(m) for m in states]
     probs = [(m, a) for m in masks for a in axes]
-    prm = ps.params(precision=ps.FP32_DC, max_sweeps=args.max_sweeps, autotune=1, progress=20)
+    # pore connectivity of every state (the analysis that pore_cleanup runs inside the solve)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pores = [ctx.pores(m, labels=False, flow=False) for m in masks]
+    torch.cuda.synchronize()
+    pores_s = time.perf_counter() - t0
+    pore_info = [{"state": i, "components": p["n_components"], "percolates": list(p["percolates"]),
+                  "flowing_fraction": [round(p["n_flowing"][j] / max(p["n_pore"], 1), 4) for j in range(3)]}
+                 for i, p in enumerate(pores)]
+    log(f"[bench] pore connectivity of {len(masks)} states: {pores_s:.2f} s")
+    prm = ps.params(precision=ps.FP32_DC, max_sweeps=args.max_sweeps, autotune=1, progress=20,
+                    pore_cleanup=args.pore_cleanup)
     if args.workload == "foam":
         # tune outside the timed solve (one pass per distinct shape)
         for m in masks:
@@ -190,7 +201,9 @@ def series_workload(args) -> dict:
             "data": "synthetic", "status": status,
             "gvox_per_s_whole_job": round(vox / wall / 1e9, 2),
             "sweep_kernel_ms": round(st["sweep_ms"], 1),
-            "config": {"workload": desc, "instances": len(res), "max_sweeps": args.max_sweeps},
+            "config": {"workload": desc, "instances": len(res), "max_sweeps": args.max_sweeps,
+                       "pore_cleanup": args.pore_cleanup},
+            "pore_connectivity_s": round(pores_s, 3), "pores": pore_info,
             "instances": inst}
 
 
@@ -214,6 +227,8 @@ def main() -> int:
                          "batched series and the large single domain")
     ap.add_argument("--max-sweeps", type=int, default=200000,
                     help="sweep budget of the series solves (--workload precipitation/foam)")
+    ap.add_argument("--pore-cleanup", type=int, choices=[0, 1], default=0,
+                    help="series workloads: sweep only the pore components that percolate along the load axis")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()

@@ -101,7 +101,13 @@ typedef struct {
     int32_t progress;   /* > 0: every `progress` checks, print one line (sweeps,
                            active instances, largest residual) to stderr; for
                            long solves.                          default 0            */
-    int32_t reserved[1];
+    int32_t pore_cleanup; /* 1: before sweeping, the pore voxels of components that
+                           do not wind around the domain along the load axis are
+                           treated as solid (see pm_pores): they carry no flow at
+                           the fixed point, so k is unchanged, and their slow
+                           transients leave the residual.  An axis along which
+                           nothing winds is PM_ERR_NO_FLOW without sweeps.  Fields
+                           of the removed voxels are returned as 0.  default 0 */
 } pm_params;
 
 /* Residual history: one record per check.  Host arrays of length cap owned by
@@ -260,6 +266,37 @@ typedef struct {
 
 /* Copy the statistics of the last call into *out (host). */
 pm_status pm_last_stats(const pm_ctx *ctx, pm_stats *out);
+
+/* ------------------------------------------------------------ pore space
+ *
+ * Connectivity of the pore space (§5.1: pre-processing removes disconnected
+ * pore space; the solver assumes percolation).  Pore voxels (mask byte 0) are
+ * connected through shared faces, across the periodic boundaries too.  A
+ * component percolates along axis j when it holds a closed path that winds
+ * around the domain along j (in the periodically repeated space it reaches a
+ * copy of its start shifted along j).  Only such components carry flow under
+ * a drive along j: in any other, p = G x_j balances the drive with v = 0.
+ */
+typedef struct {
+    int64_t n_pore;                   /* pore voxels                                    */
+    int64_t n_components;             /* pore components                                */
+    int32_t percolates[3];            /* axis j: some component winds along j           */
+    int32_t reserved;
+    int64_t n_flowing[3];             /* pore voxels of components winding along j      */
+    int64_t n_flowing_components[3];  /* components winding along j                     */
+} pm_pore_info;
+
+/*
+ * mask: device uint8 [nz][ny][nx].  labels: device int64 [nz][ny][nx] or NULL;
+ * receives for each pore voxel the smallest linear index of its component, -1
+ * for solid voxels.  flow: device uint8 [nz][ny][nx] or NULL; bit j (value
+ * 1 << j) set for pore voxels of components winding along j, 0 elsewhere.
+ * info: host, required.  Scratch: about 17 bytes per voxel.  Synchronises the
+ * stream.  Errors: PM_ERR_ARG (NULL mask or info, bad dims, misaligned labels),
+ * PM_ERR_OOM, PM_ERR_DEVICE.
+ */
+pm_status pm_pores(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz,
+                   int64_t *labels, uint8_t *flow, pm_pore_info *info);
 
 /* ------------------------------------------------------------ principal axes
  *

@@ -30,7 +30,7 @@ KERNEL_AUTO, KERNEL_FUSED, KERNEL_SIMPLE = 0, 1, 2
 EXPORTS = ("pm_params_default", "pm_status_string", "pm_create", "pm_destroy", "pm_last_error",
            "pm_mem_used", "pm_preprocess", "pm_face_codes", "pm_iterate", "pm_residual", "pm_solve",
            "pm_tensor", "pm_solve_batch", "pm_last_stats", "pm_autotune", "pm_principal_axes",
-           "pm_plane_angle")
+           "pm_plane_angle", "pm_pores")
 ISOTROPIC, TRANSVERSE, ORTHOTROPIC = 0, 1, 2
 CLASS_NAMES = {ISOTROPIC: "isotropic", TRANSVERSE: "transverse", ORTHOTROPIC: "orthotropic"}
 
@@ -54,7 +54,7 @@ class PmParams(ctypes.Structure):
         ("graphs", ctypes.c_int32),
         ("autotune", ctypes.c_int32),
         ("progress", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 1),
+        ("pore_cleanup", ctypes.c_int32),
     ]
 
 
@@ -101,6 +101,17 @@ class PmStats(ctypes.Structure):
         ("tile_y", ctypes.c_int32),
         ("zchunk", ctypes.c_int32),
         ("precision", ctypes.c_int32),
+    ]
+
+
+class PmPoreInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_pore", ctypes.c_int64),
+        ("n_components", ctypes.c_int64),
+        ("percolates", ctypes.c_int32 * 3),
+        ("reserved", ctypes.c_int32),
+        ("n_flowing", ctypes.c_int64 * 3),
+        ("n_flowing_components", ctypes.c_int64 * 3),
     ]
 
 
@@ -161,6 +172,8 @@ def load_library(path: str = LIB_PATH):
     lib.pm_last_stats.restype = i32
     lib.pm_autotune.argtypes = [vp, vp, vp, i64, i64, i64, i32, vp]
     lib.pm_autotune.restype = i32
+    lib.pm_pores.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, ctypes.POINTER(PmPoreInfo)]
+    lib.pm_pores.restype = i32
     d9 = ctypes.c_double * 9
     lib.pm_principal_axes.argtypes = [ctypes.POINTER(d9), ctypes.c_double, ctypes.POINTER(PmPrincipal)]
     lib.pm_principal_axes.restype = i32
@@ -381,6 +394,22 @@ class Context:
             hists.append({"sweep": sw_[:n].copy(), "r": r_[:n].copy(), "eps": e_[:n].copy(),
                           "q": q_[:3 * n].reshape(n, 3).copy()})
         return TensorResult(STATUS_NAMES[st], k.reshape(3, 3), ks.reshape(3, 3), sw, hists)
+
+    def pores(self, mask, labels: bool = True, flow: bool = True) -> dict:
+        """Pore components and percolation (pm_pores): counts, per-axis flags, and
+        optionally the label (int64) and flow-bit (uint8) volumes as device tensors."""
+        m, nx, ny, nz = _mask3(mask)
+        lab = torch.empty(m.shape, dtype=torch.int64, device=m.device) if labels else None
+        fl = torch.empty(m.shape, dtype=torch.uint8, device=m.device) if flow else None
+        info = PmPoreInfo()
+        st = self._lib.pm_pores(self._h, _stream(), m.data_ptr(), nx, ny, nz,
+                                lab.data_ptr() if lab is not None else None,
+                                fl.data_ptr() if fl is not None else None, ctypes.byref(info))
+        self._check(st)
+        return {"n_pore": info.n_pore, "n_components": info.n_components,
+                "percolates": tuple(bool(x) for x in info.percolates),
+                "n_flowing": tuple(info.n_flowing), "n_flowing_components": tuple(info.n_flowing_components),
+                "labels": lab, "flow": fl}
 
     def solve_batch(self, problems, prm: PmParams | None = None, hist_cap: int = 100000,
                     fields=None):

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libporestokes.so")
-SOURCES = ["kernels.hip", "api.hip", "principal.hip"]
+SOURCES = ["kernels.hip", "api.hip", "principal.hip", "pores.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -192,6 +192,7 @@ pm_status check_params(pm_ctx *ctx, const pm_params *p)
     if (p->zchunk < 0) return fail(ctx, PM_ERR_ARG, "zchunk must be >= 0");
     if (p->graphs != 0 && p->graphs != 1) return fail(ctx, PM_ERR_ARG, "graphs must be 0 or 1");
     if (p->progress < 0) return fail(ctx, PM_ERR_ARG, "progress must be >= 0");
+    if (p->pore_cleanup != 0 && p->pore_cleanup != 1) return fail(ctx, PM_ERR_ARG, "pore_cleanup must be 0 or 1");
     return PM_OK;
 }
 
@@ -910,6 +911,164 @@ pm_status check_instance_args(pm_ctx *ctx, const uint8_t *mask, int64_t nx, int6
     return PM_OK;
 }
 
+// ------------------------------------------------------------ pore connectivity
+//
+// Which pore components wind around the periodic domain along each axis
+// (percolate), from a labelling of the whole domain and, per axis j, one with
+// the periodic connection across j cut.  Cut across j, a component's pieces
+// (cut components) are joined only by the boundary-crossing pairs; give each
+// piece a potential, the number of periods its copy is shifted along j, with
+// every crossing from coordinate n_j - 1 to 0 demanding +1.  A set of pieces
+// whose crossings cannot all be satisfied contains a closed path with nonzero
+// winding along j: its component percolates along j.
+struct WindingSets {
+    std::vector<int64_t> par, pot;  // pot[x] = potential(x) - potential(par[x])
+    std::vector<char> bad;
+    explicit WindingSets(size_t n) : par(n), pot(n, 0), bad(n, 0)
+    {
+        for (size_t i = 0; i < n; ++i) par[i] = (int64_t)i;
+    }
+    int64_t find(int64_t x, int64_t *px)
+    {
+        int64_t r = x, acc = 0;
+        while (par[r] != r) {
+            acc += pot[r];
+            r = par[r];
+        }
+        int64_t y = x, accy = acc;
+        while (par[y] != y) {  // compress, keeping potentials relative to the root
+            const int64_t next = par[y], py = pot[y];
+            par[y] = r;
+            pot[y] = accy;
+            accy -= py;
+            y = next;
+        }
+        *px = acc;
+        return r;
+    }
+    void cross(int64_t a, int64_t b)  // potential(b) = potential(a) + 1
+    {
+        int64_t pa, pb;
+        const int64_t ra = find(a, &pa), rb = find(b, &pb);
+        if (ra == rb) {
+            if (pb - pa != 1) bad[ra] = 1;
+        } else {
+            par[rb] = ra;
+            pot[rb] = pa + 1 - pb;
+            bad[ra] = (char)(bad[ra] | bad[rb]);
+        }
+    }
+};
+
+// Flow flags of a mask's pore space: flow[t] bit j set for a pore voxel whose
+// component winds along j; labels (device, N, may be null) receive the
+// component labels; info (host) the counts.  flow is required.
+pm_status pore_flow(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx, int ny, int nz, int64_t *labels,
+                    uint8_t *flow, pm_pore_info *info)
+{
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t dims[3] = {nx, ny, nz};
+    Scratch scratch(ctx);
+    void *p = nullptr;
+    int64_t *lab = labels;
+    if (!lab) {
+        PM_TRY(scratch.get((size_t)N * sizeof(int64_t), &p));
+        lab = (int64_t *)p;
+    }
+    int64_t max_cells = 0;
+    for (int j = 0; j < 3; ++j) max_cells = std::max(max_cells, N / dims[j]);
+    int64_t *cut = nullptr, *pairs = nullptr, *dlist = nullptr, *dout = nullptr;
+    uint8_t *lflag = nullptr;
+    unsigned long long *counts = nullptr;
+    PM_TRY(scratch.get((size_t)N * sizeof(int64_t), &p));
+    cut = (int64_t *)p;
+    PM_TRY(scratch.get((size_t)max_cells * 2 * sizeof(int64_t), &p));
+    pairs = (int64_t *)p;
+    PM_TRY(scratch.get((size_t)N, &p));
+    lflag = (uint8_t *)p;
+    PM_TRY(scratch.get(5 * sizeof(unsigned long long), &p));
+    counts = (unsigned long long *)p;
+    PM_HIP(hipMemsetAsync(lflag, 0, (size_t)N, s));
+    int *changed = nullptr;
+    PM_TRY(scratch.get(sizeof(int), &p));
+    changed = (int *)p;
+    // label, then jump until every label is a root (one round when the labelling settled)
+    auto label = [&](int cut_axis, int64_t *out) -> pm_status {
+        PM_HIP(launch_cc_label(mask, nx, ny, nz, cut_axis, out, s));
+        for (int round = 0;; ++round) {
+            if (round == 64) return fail(ctx, PM_ERR_DEVICE, "pore labelling did not settle");
+            int h = 0;
+            PM_HIP(launch_cc_jump(out, N, changed, s));
+            PM_HIP(hipMemcpyAsync(&h, changed, sizeof h, hipMemcpyDeviceToHost, s));
+            PM_HIP(hipStreamSynchronize(s));
+            if (!h) return PM_OK;
+        }
+    };
+    PM_TRY(label(-1, lab));
+    std::memset(info, 0, sizeof *info);
+    std::vector<int64_t> hp((size_t)max_cells * 2);
+    for (int j = 0; j < 3; ++j) {
+        const int64_t cells = N / dims[j];
+        PM_TRY(label(j, cut));
+        PM_HIP(launch_cc_cross(mask, nx, ny, nz, j, cut, pairs, s));
+        PM_HIP(hipMemcpyAsync(hp.data(), pairs, (size_t)cells * 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        PM_HIP(hipStreamSynchronize(s));
+        // distinct crossing pairs, then the cut components they mention, densely numbered
+        std::vector<std::pair<int64_t, int64_t>> pr;
+        pr.reserve((size_t)cells);
+        for (int64_t i = 0; i < cells; ++i)
+            if (hp[2 * i] >= 0) pr.emplace_back(hp[2 * i], hp[2 * i + 1]);
+        std::sort(pr.begin(), pr.end());
+        pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+        std::vector<int64_t> ids;
+        ids.reserve(2 * pr.size());
+        for (auto &e : pr) {
+            ids.push_back(e.first);
+            ids.push_back(e.second);
+        }
+        std::sort(ids.begin(), ids.end());
+        ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+        auto dense = [&](int64_t l) { return (int64_t)(std::lower_bound(ids.begin(), ids.end(), l) - ids.begin()); };
+        WindingSets ws(ids.size());
+        for (auto &e : pr) ws.cross(dense(e.first), dense(e.second));
+        // one cut component of every winding set: its whole-domain label is the component's
+        std::vector<int64_t> reps;
+        for (size_t i = 0; i < ids.size(); ++i) {
+            int64_t pot;
+            const int64_t r = ws.find((int64_t)i, &pot);
+            if (r == (int64_t)i && ws.bad[r]) reps.push_back(ids[i]);
+        }
+        std::vector<int64_t> plabs(reps.size());
+        if (!reps.empty()) {
+            Scratch lists(ctx);
+            PM_TRY(lists.get(reps.size() * sizeof(int64_t), &p));
+            dlist = (int64_t *)p;
+            PM_TRY(lists.get(reps.size() * sizeof(int64_t), &p));
+            dout = (int64_t *)p;
+            PM_HIP(hipMemcpyAsync(dlist, reps.data(), reps.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+            PM_HIP(launch_gather_i64(lab, dlist, (int64_t)reps.size(), dout, s));
+            PM_HIP(hipMemcpyAsync(plabs.data(), dout, reps.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            PM_HIP(hipStreamSynchronize(s));
+            std::sort(plabs.begin(), plabs.end());
+            plabs.erase(std::unique(plabs.begin(), plabs.end()), plabs.end());
+            PM_HIP(hipMemcpyAsync(dlist, plabs.data(), plabs.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+            PM_HIP(launch_flag_labels(dlist, (int64_t)plabs.size(), j, lflag, s));
+            PM_HIP(hipStreamSynchronize(s));  // the list buffers are freed at the end of this scope
+        }
+        info->percolates[j] = plabs.empty() ? 0 : 1;
+        info->n_flowing_components[j] = (int64_t)plabs.size();
+    }
+    PM_HIP(launch_flow_bits(lab, lflag, N, flow, s));
+    PM_HIP(launch_pore_counts(lab, flow, N, counts, s));
+    unsigned long long hc[5];
+    PM_HIP(hipMemcpyAsync(hc, counts, sizeof hc, hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    info->n_pore = (int64_t)hc[0];
+    info->n_components = (int64_t)hc[1];
+    for (int j = 0; j < 3; ++j) info->n_flowing[j] = (int64_t)hc[2 + j];
+    return PM_OK;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -967,6 +1126,28 @@ pm_status pm_create(int hip_device, size_t mem_cap_bytes, pm_ctx **out)
         return PM_ERR_DEVICE;
     }
     *out = ctx;
+    return PM_OK;
+}
+
+pm_status pm_pores(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz,
+                   int64_t *labels, uint8_t *flow, pm_pore_info *info)
+{
+    if (!ctx) return PM_ERR_ARG;
+    ctx->err.clear();
+    if (!mask || !info) return fail(ctx, PM_ERR_ARG, "mask and info must not be NULL");
+    PM_TRY(check_dims(ctx, nx, ny, nz));
+    if (labels && !aligned(labels, 8)) return fail(ctx, PM_ERR_ARG, "labels is misaligned");
+    PM_TRY(set_device(ctx));
+    hipStream_t s = (hipStream_t)stream;
+    Scratch scratch(ctx);
+    uint8_t *fl = flow;
+    if (!fl) {
+        void *p = nullptr;
+        PM_TRY(scratch.get((size_t)(nx * ny * nz), &p));
+        fl = (uint8_t *)p;
+    }
+    PM_TRY(pore_flow(ctx, s, mask, (int)nx, (int)ny, (int)nz, labels, fl, info));
+    PM_HIP(hipStreamSynchronize(s));
     return PM_OK;
 }
 
@@ -1194,6 +1375,30 @@ pm_status pm_solve_batch(pm_ctx *ctx, void *stream, pm_instance *insts, int32_t 
         if (in.hist) in.hist->n = 0;
     }
     PM_TRY(set_device(ctx));
+    // pore cleanup: each instance sweeps a copy of its mask in which the pore
+    // components that do not wind along its load axis are solid
+    Scratch cleaned(ctx);
+    if (params->pore_cleanup) {
+        std::map<const uint8_t *, uint8_t *> flow_of;
+        for (Inst &in : list) {
+            uint8_t *flow = nullptr;
+            auto it = flow_of.find(in.mask);
+            if (it != flow_of.end()) {
+                flow = it->second;
+            } else {
+                void *p = nullptr;
+                PM_TRY(cleaned.get((size_t)in.N, &p));
+                flow = (uint8_t *)p;
+                pm_pore_info info;
+                PM_TRY(pore_flow(ctx, (hipStream_t)stream, in.mask, in.nx, in.ny, in.nz, nullptr, flow, &info));
+                flow_of[in.mask] = flow;
+            }
+            void *p = nullptr;
+            PM_TRY(cleaned.get((size_t)in.N, &p));
+            PM_HIP(launch_clean_mask(flow, in.N, in.axis, (uint8_t *)p, (hipStream_t)stream));
+            in.mask = (const uint8_t *)p;
+        }
+    }
     if (params->autotune && !(params->tile_x && params->tile_y) && params->zchunk == 0) {
         std::vector<Prec> precs;
         if (params->precision != PM_FP64) precs.push_back(kF32);

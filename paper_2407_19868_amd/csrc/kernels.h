@@ -64,4 +64,21 @@ hipError_t launch_state_sums(Prec prec, int nx, int ny, int nz, int axis, const 
                              int64_t *nblocks, hipStream_t s);
 int64_t state_sums_blocks(int64_t n);
 
+// ---- pore-space connectivity (pores.hip)
+// labels[t]: smallest index of t's pore component, -1 for solid; cut = axis whose
+// periodic connection is dropped, -1 for none
+hipError_t launch_cc_label(const uint8_t *mask, int nx, int ny, int nz, int cut, int64_t *labels, hipStream_t s);
+// one round of pointer jumping over the labels; *changed (device int) = 1 if any label moved
+hipError_t launch_cc_jump(int64_t *labels, int64_t n, int *changed, hipStream_t s);
+// 2 x (cells of the boundary plane of axis j) labels of the voxel pairs joined across that boundary
+hipError_t launch_cc_cross(const uint8_t *mask, int nx, int ny, int nz, int j, const int64_t *labels, int64_t *pairs,
+                           hipStream_t s);
+hipError_t launch_gather_i64(const int64_t *src, const int64_t *idx, int64_t m, int64_t *out, hipStream_t s);
+hipError_t launch_flag_labels(const int64_t *lab, int64_t m, int j, uint8_t *lflag, hipStream_t s);
+hipError_t launch_flow_bits(const int64_t *labels, const uint8_t *lflag, int64_t n, uint8_t *flow, hipStream_t s);
+// counts (device, 5 x uint64, zeroed by the launcher): pore voxels, components, flow voxels per axis
+hipError_t launch_pore_counts(const int64_t *labels, const uint8_t *flow, int64_t n, unsigned long long *counts,
+                              hipStream_t s);
+hipError_t launch_clean_mask(const uint8_t *flow, int64_t n, int j, uint8_t *cleaned, hipStream_t s);
+
 }  // namespace ps

@@ -44,9 +44,10 @@ def test_struct_layouts_match_header():
     import tempfile
 
     import paper_2407_19868_amd as ps
-    src = ('#include "porestokes.h"\n#include <stdio.h>\n'
-           'int main(){printf("%zu %zu %zu %zu\\n", sizeof(pm_params), sizeof(pm_history),'
-           ' sizeof(pm_instance), sizeof(pm_stats));return 0;}\n')
+    src = ('#include "porestokes.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+           'int main(){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(pm_params), sizeof(pm_history),'
+           ' sizeof(pm_instance), sizeof(pm_stats), sizeof(pm_pore_info), sizeof(pm_principal),'
+           ' offsetof(pm_params, pore_cleanup));return 0;}\n')
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
         exe = os.path.join(d, "t")
@@ -54,7 +55,8 @@ def test_struct_layouts_match_header():
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         sizes = [int(x) for x in subprocess.check_output([exe]).split()]
     assert sizes == [ctypes.sizeof(ps.PmParams), ctypes.sizeof(ps.PmHistory),
-                     ctypes.sizeof(ps.PmInstance), ctypes.sizeof(ps.PmStats)]
+                     ctypes.sizeof(ps.PmInstance), ctypes.sizeof(ps.PmStats), ctypes.sizeof(ps.PmPoreInfo),
+                     ctypes.sizeof(ps.PmPrincipal), ps.PmParams.pore_cleanup.offset]
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
