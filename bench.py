@@ -181,9 +181,10 @@ def series_workload(args) -> dict:
                     pore_cleanup=args.pore_cleanup)
     if args.workload == "foam":
         # tune outside the timed solve (one pass per distinct shape)
-        for m in masks:
+        for i, m in enumerate(masks):
             for pr in (ps.FP32, ps.FP64):
-                ctx.autotune(m, pr)
+                best = ctx.autotune(m, pr)
+                log(f"[bench] autotuned state {i} {tuple(m.shape)} {'fp32' if pr == ps.FP32 else 'fp64'}: {best}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     status, res = ctx.solve_batch(probs, prm)

@@ -345,3 +345,15 @@ def test_batch_clogged_instance_only_changes_its_status(ctx):
     assert abs(res[1]["kcol"][0]) < 1e-6 * res[0]["kcol"][0]
     single = ctx.solve(probs[0][0], 0)
     assert np.array_equal(res[0]["kcol"], single.kcol)
+
+
+def test_fp32_dc_stays_fp32_far_above_its_floor(ctx):
+    """A very open foam (k ~ 55 voxel^2) converges slowly from r = 1; its FP32
+    floor lies near 2^-24 |q| / (dt G) ~ 1e-4.  After 1500 sweeps r is still
+    ~0.7: the FP32 phase must go on (the slowly decelerating residual once
+    passed for a plateau and handed over to FP64 sweeps at r ~ 0.7)."""
+    m = synth.foam_series()[7]
+    r = ctx.solve(ps.to_device(m), 2, ps.params(precision=ps.FP32_DC, max_sweeps=1500, tol=1e-12))
+    assert r.status == "NOT_CONVERGED"
+    assert r.hist_r[-1] > 1e-2
+    assert ctx.last_stats()["precision"] == ps.FP32
