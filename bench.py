@@ -139,7 +139,9 @@ def series_workload(args) -> dict:
                          "hbm_frac": round(gv * BYTES_PER_VOXEL[form] / HBM_PEAK_GBS, 4),
                          "gvox_per_s_wall": round(N * (args.sweeps_per_step // 5) / wall / 1e9, 2),
                          "tile": [st["tile_x"], st["tile_y"], st["zchunk"]],
-                         "device_bytes_held": None}
+                         "library_peak_bytes": int(st["peak_bytes"]),
+                         "caller_field_bytes": int(4 * N * (4 if prec == ps.FP32 else 8)),
+                         "mask_bytes": int(N)}
             log(f"[bench] 1536^3 {form}: {gv:.1f} GVox/s ({100 * res[form]['hbm_frac']:.1f}% HBM)")
             del f
             torch.cuda.empty_cache()
@@ -365,9 +367,34 @@ def main() -> int:
                                 "ratio_III_I": round(pa.ratio, 5), "rel_tol": 0.05}
         out["time_to_tensor"] = tt
 
+        # the small single solve: 32^3 packing, load along x, FP64 to r < 1e-8 (launch-latency bound)
+        c1_np = synth.single_spheres_32()
+        c1 = ps.to_device(c1_np)
+        ctx.solve(c1, 0, ps.params())  # first use of this shape
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r1 = ctx.solve(c1, 0, ps.params())
+        torch.cuda.synchronize()
+        dt1 = time.perf_counter() - t0
+        out["single_solve_32"] = {"workload": "overlapping spheres 32^3, radius 4, porosity 0.40, seed 1; "
+                                              "load axis x; FP64, r < 1e-8",
+                                  "seconds": round(dt1, 4), "status": r1.status, "sweeps": int(r1.sweeps),
+                                  "us_per_sweep": round(dt1 / max(r1.sweeps, 1) * 1e6, 2),
+                                  "k_col": [float(f"{x:.12g}") for x in r1.kcol]}
+        log(f"[bench] 32^3 single solve: {dt1 * 1e3:.1f} ms, {r1.sweeps} sweeps")
+
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(mask_np, args.cpu_seconds)
+        if "single_solve_32" in out:
+            import oracle
+            t0 = time.perf_counter()
+            o1 = oracle.solve(c1_np, 0, oracle.params())
+            dto = time.perf_counter() - t0
+            out["cpu_baseline"]["single_solve_32"] = {
+                "seconds": round(dto, 3), "status": o1.status, "sweeps": int(o1.sweeps),
+                "k_rel_diff_gpu": float(np.abs(np.asarray(o1.kcol) - r1.kcol).max() / np.abs(o1.kcol).max())}
+            log(f"[bench] oracle 32^3 single solve: {dto:.2f} s")
         log(f"[bench] oracle {out['cpu_baseline']['value']:.4f} GVox/s on "
             f"{out['cpu_baseline']['cores']} threads")
     ctx.close()

@@ -262,6 +262,8 @@ typedef struct {
     double total_ms;         /* host wall time of the call                             */
     int32_t tile_x, tile_y, zchunk;  /* decomposition of the last instance             */
     int32_t precision;       /* pm_precision of the last sweep launch (PM_FP64/PM_FP32) */
+    int64_t peak_bytes;      /* most device memory the library held during the call
+                                (its own allocations, not the caller's buffers)          */
 } pm_stats;
 
 /* Copy the statistics of the last call into *out (host). */

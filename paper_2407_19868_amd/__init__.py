@@ -101,6 +101,7 @@ class PmStats(ctypes.Structure):
         ("tile_y", ctypes.c_int32),
         ("zchunk", ctypes.c_int32),
         ("precision", ctypes.c_int32),
+        ("peak_bytes", ctypes.c_int64),
     ]
 
 

@@ -78,6 +78,7 @@ pm_status dalloc(pm_ctx *ctx, size_t bytes, void **out)
     }
     ctx->allocs[*out] = bytes;
     ctx->used += bytes;
+    if ((int64_t)ctx->used > ctx->stats.peak_bytes) ctx->stats.peak_bytes = (int64_t)ctx->used;
     return PM_OK;
 }
 
@@ -133,6 +134,7 @@ void stats_begin(pm_ctx *ctx)
 {
     std::memset(&ctx->stats, 0, sizeof ctx->stats);
     ctx->stats.total_ms = -now_ms();
+    ctx->stats.peak_bytes = (int64_t)ctx->used;
 }
 
 void stats_end(pm_ctx *ctx) { ctx->stats.total_ms += now_ms(); }
@@ -1416,6 +1418,7 @@ pm_status pm_solve_batch(pm_ctx *ctx, void *stream, pm_instance *insts, int32_t 
         if (in.hist) in.hist->n = 0;
     }
     PM_TRY(set_device(ctx));
+    stats_begin(ctx);
     // pore cleanup: each instance sweeps a copy of its mask in which the pore
     // components that do not wind along its load axis are solid
     Scratch cleaned(ctx);
@@ -1449,7 +1452,6 @@ pm_status pm_solve_batch(pm_ctx *ctx, void *stream, pm_instance *insts, int32_t 
                 if (!ctx->tune.count(tune_key(in.nx, in.ny, in.nz, pr)))
                     PM_TRY(autotune_shape(ctx, (hipStream_t)stream, in.mask, in.nx, in.ny, in.nz, pr, nullptr));
     }
-    stats_begin(ctx);
     pm_status rs;
     {
         Engine eng(ctx, (hipStream_t)stream, params, list);
