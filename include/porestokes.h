@@ -108,6 +108,19 @@ typedef struct {
                            transients leave the residual.  An axis along which
                            nothing winds is PM_ERR_NO_FLOW without sweeps.  Fields
                            of the removed voxels are returned as 0.  default 0 */
+    int32_t outer_walls;  /* bit i (1 << i): no-slip, no-penetration walls at both ends
+                           of axis i instead of the periodic connection (§4 lists
+                           such outer walls beside periodic ones).  Realised
+                           exactly by sweeping the mask with one solid layer
+                           appended along each wall axis: a wall lies half a voxel
+                           beyond the first and the last layer, and every stencil
+                           position beyond it is solid (so the App. B cases 7 and 8
+                           never arise).  Fields are returned on the caller's grid;
+                           k is the mean flux over the caller's voxels.  A load
+                           axis with walls carries no through-flow: that solve is
+                           PM_ERR_NO_FLOW without sweeps.  Solves only (pm_iterate
+                           and pm_residual reject it).            default 0 */
+    int32_t reserved[1];
 } pm_params;
 
 /* Residual history: one record per check.  Host arrays of length cap owned by
@@ -268,6 +281,18 @@ typedef struct {
 
 /* Copy the statistics of the last call into *out (host). */
 pm_status pm_last_stats(const pm_ctx *ctx, pm_stats *out);
+
+/*
+ * Mirroring (§5.1 pre-processing "mirroring for symmetric periodicity"; the
+ * mirrored samples of §7.1): the sample followed by its mirror image along every
+ * axis i with bit i of `axes`, so that the periodic cell is continuous across
+ * its boundaries.  out: device uint8 [mz][my][mx], m_i = 2 n_i for mirrored axes,
+ * n_i otherwise; out at coordinate c >= n_i equals the sample at 2 n_i - 1 - c.
+ * Only enqueues work.  Errors: PM_ERR_ARG (NULL pointers, axes outside 0..7,
+ * dims too large after doubling).
+ */
+pm_status pm_mirror(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz, int axes,
+                    uint8_t *out);
 
 /* ------------------------------------------------------------ pore space
  *

@@ -292,3 +292,25 @@ def tensor(mask, prm: OrcParams | None = None):
         res.append(r)
     k = np.stack(cols, axis=1)
     return k, 0.5 * (k + k.T), res
+
+
+def solve_walls(mask, axis: int, walls: int, prm: OrcParams | None = None) -> Result:
+    """§4: no-slip, no-penetration outer walls at both ends of every axis i with
+    bit i of `walls` set.  Written out as the same iteration on the mask with
+    one solid layer appended along each wall axis (the wall half a voxel beyond
+    the last layer; its periodic image half a voxel before the first), then the
+    fields cut back to the original grid and the fluxes averaged over the
+    original voxels.  A load axis with walls has no through-flow: NO_FLOW."""
+    m = _mask(mask)
+    if (walls >> axis) & 1:
+        z = State.zeros(m.shape)
+        return Result("NO_FLOW", np.zeros(3), 0, z, np.zeros(0, np.int64), np.zeros(0), np.zeros(0),
+                      np.zeros((0, 3)))
+    pad = [(0, (walls >> 2) & 1), (0, (walls >> 1) & 1), (0, walls & 1)]  # (z, y, x)
+    mp = np.pad(m, pad, mode="constant", constant_values=1)
+    r = solve(mp, axis, prm)
+    nz, ny, nx = m.shape
+    scale = mp.size / m.size
+    st = State(*(a[:nz, :ny, :nx].copy() for a in r.state.arrays()))
+    return Result(r.status, r.kcol * scale, r.sweeps, st, r.hist_sweep, r.hist_r, r.hist_eps,
+                  r.hist_q * scale)

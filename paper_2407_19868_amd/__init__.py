@@ -30,7 +30,7 @@ KERNEL_AUTO, KERNEL_FUSED, KERNEL_SIMPLE = 0, 1, 2
 EXPORTS = ("pm_params_default", "pm_status_string", "pm_create", "pm_destroy", "pm_last_error",
            "pm_mem_used", "pm_preprocess", "pm_face_codes", "pm_iterate", "pm_residual", "pm_solve",
            "pm_tensor", "pm_solve_batch", "pm_last_stats", "pm_autotune", "pm_principal_axes",
-           "pm_plane_angle", "pm_pores")
+           "pm_plane_angle", "pm_pores", "pm_mirror")
 ISOTROPIC, TRANSVERSE, ORTHOTROPIC = 0, 1, 2
 CLASS_NAMES = {ISOTROPIC: "isotropic", TRANSVERSE: "transverse", ORTHOTROPIC: "orthotropic"}
 
@@ -55,6 +55,8 @@ class PmParams(ctypes.Structure):
         ("autotune", ctypes.c_int32),
         ("progress", ctypes.c_int32),
         ("pore_cleanup", ctypes.c_int32),
+        ("outer_walls", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 
@@ -173,6 +175,8 @@ def load_library(path: str = LIB_PATH):
     lib.pm_last_stats.restype = i32
     lib.pm_autotune.argtypes = [vp, vp, vp, i64, i64, i64, i32, vp]
     lib.pm_autotune.restype = i32
+    lib.pm_mirror.argtypes = [vp, vp, vp, i64, i64, i64, i32, vp]
+    lib.pm_mirror.restype = i32
     lib.pm_pores.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, ctypes.POINTER(PmPoreInfo)]
     lib.pm_pores.restype = i32
     d9 = ctypes.c_double * 9
@@ -395,6 +399,14 @@ class Context:
             hists.append({"sweep": sw_[:n].copy(), "r": r_[:n].copy(), "eps": e_[:n].copy(),
                           "q": q_[:3 * n].reshape(n, 3).copy()})
         return TensorResult(STATUS_NAMES[st], k.reshape(3, 3), ks.reshape(3, 3), sw, hists)
+
+    def mirror(self, mask, axes: int) -> torch.Tensor:
+        """The sample followed by its mirror image along every axis in the bit mask (pm_mirror)."""
+        m, nx, ny, nz = _mask3(mask)
+        shape = (nz * (2 if axes & 4 else 1), ny * (2 if axes & 2 else 1), nx * (2 if axes & 1 else 1))
+        out = torch.empty(shape, dtype=torch.uint8, device=m.device)
+        self._check(self._lib.pm_mirror(self._h, _stream(), m.data_ptr(), nx, ny, nz, int(axes), out.data_ptr()))
+        return out
 
     def pores(self, mask, labels: bool = True, flow: bool = True) -> dict:
         """Pore components and percolation (pm_pores): counts, per-axis flags, and

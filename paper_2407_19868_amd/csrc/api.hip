@@ -195,6 +195,7 @@ pm_status check_params(pm_ctx *ctx, const pm_params *p)
     if (p->graphs != 0 && p->graphs != 1) return fail(ctx, PM_ERR_ARG, "graphs must be 0 or 1");
     if (p->progress < 0) return fail(ctx, PM_ERR_ARG, "progress must be >= 0");
     if (p->pore_cleanup != 0 && p->pore_cleanup != 1) return fail(ctx, PM_ERR_ARG, "pore_cleanup must be 0 or 1");
+    if (p->outer_walls < 0 || p->outer_walls > 7) return fail(ctx, PM_ERR_ARG, "outer_walls must be a bit mask 0..7");
     return PM_OK;
 }
 
@@ -312,6 +313,7 @@ struct Inst {
     // derived
     uint32_t *codes = nullptr;
     int64_t nflow = 0, nsolid = 0;
+    bool no_through_flow = false;  // outer walls close the load axis
     // state
     bool dc = false;
     Prec prec = kF64;
@@ -468,7 +470,7 @@ struct Engine {
             in.nsolid = (int64_t)hc[4 * i];
             in.nflow = (int64_t)hc[4 * i + 1 + in.axis];
             in.active = true;
-            if (in.nsolid == 0 || in.nflow == 0) {
+            if (in.no_through_flow || in.nsolid == 0 || in.nflow == 0) {
                 in.status = PM_ERR_NO_FLOW;
                 in.active = false;
             }
@@ -1172,6 +1174,20 @@ pm_status pm_create(int hip_device, size_t mem_cap_bytes, pm_ctx **out)
     return PM_OK;
 }
 
+pm_status pm_mirror(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz, int axes,
+                    uint8_t *out)
+{
+    if (!ctx) return PM_ERR_ARG;
+    ctx->err.clear();
+    if (!mask || !out) return fail(ctx, PM_ERR_ARG, "mask and out must not be NULL");
+    if (axes < 0 || axes > 7) return fail(ctx, PM_ERR_ARG, "axes must be a bit mask 0..7");
+    PM_TRY(check_dims(ctx, nx, ny, nz));
+    PM_TRY(check_dims(ctx, (axes & 1) ? 2 * nx : nx, (axes & 2) ? 2 * ny : ny, (axes & 4) ? 2 * nz : nz));
+    PM_TRY(set_device(ctx));
+    PM_HIP(launch_mirror(mask, (int)nx, (int)ny, (int)nz, axes, out, (hipStream_t)stream));
+    return PM_OK;
+}
+
 pm_status pm_pores(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz,
                    int64_t *labels, uint8_t *flow, pm_pore_info *info)
 {
@@ -1249,6 +1265,7 @@ pm_status pm_iterate(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx,
     ctx->err.clear();
     PM_TRY(check_params(ctx, params));
     if (params->precision == PM_FP32_DC) return fail(ctx, PM_ERR_ARG, "pm_iterate takes PM_FP64 or PM_FP32");
+    if (params->outer_walls) return fail(ctx, PM_ERR_ARG, "outer_walls applies to solves (pm_solve, pm_tensor, pm_solve_batch)");
     const Prec prec = params->precision == PM_FP64 ? kF64 : kF32;
     void *f[4] = {u, v, w, p};
     PM_TRY(check_instance_args(ctx, mask, nx, ny, nz, axis, 1.0, 1.0, f, true, elem(prec)));
@@ -1337,6 +1354,7 @@ pm_status pm_residual(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx
     ctx->err.clear();
     PM_TRY(check_params(ctx, params));
     if (params->precision == PM_FP32_DC) return fail(ctx, PM_ERR_ARG, "pm_residual takes PM_FP64 or PM_FP32");
+    if (params->outer_walls) return fail(ctx, PM_ERR_ARG, "outer_walls applies to solves (pm_solve, pm_tensor, pm_solve_batch)");
     if (!out) return fail(ctx, PM_ERR_ARG, "out is NULL");
     const Prec prec = params->precision == PM_FP64 ? kF64 : kF32;
     void *f[4] = {(void *)u, (void *)v, (void *)w, (void *)p};
@@ -1419,6 +1437,56 @@ pm_status pm_solve_batch(pm_ctx *ctx, void *stream, pm_instance *insts, int32_t 
     }
     PM_TRY(set_device(ctx));
     stats_begin(ctx);
+    // outer walls: sweep each instance on its grid with one solid layer appended
+    // along every wall axis; the fields come back to the caller's grid afterwards
+    struct Walled {
+        int nx = 0, ny = 0, nz = 0;
+        int64_t N = 0;
+        void *user[4] = {nullptr, nullptr, nullptr, nullptr};
+    };
+    std::vector<Walled> walled(list.size());
+    Scratch wall_scratch(ctx);
+    const int W = params->outer_walls;
+    const size_t wall_ue = params->precision == PM_FP32 ? sizeof(float) : sizeof(double);
+    if (W) {
+        std::map<const uint8_t *, const uint8_t *> padded_of;
+        for (size_t i = 0; i < list.size(); ++i) {
+            Inst &in = list[i];
+            Walled &w = walled[i];
+            w.nx = in.nx;
+            w.ny = in.ny;
+            w.nz = in.nz;
+            w.N = in.N;
+            for (int f = 0; f < 4; ++f) w.user[f] = in.user[f];
+            const int px = in.nx + (W & 1), py = in.ny + ((W >> 1) & 1), pz = in.nz + ((W >> 2) & 1);
+            PM_TRY(check_dims(ctx, px, py, pz));
+            const int64_t Np = (int64_t)px * py * pz;
+            void *p = nullptr;
+            auto it = padded_of.find(in.mask);
+            if (it != padded_of.end()) {
+                in.mask = it->second;
+            } else {
+                PM_TRY(wall_scratch.get((size_t)Np, &p));
+                PM_HIP(launch_pad_mask(in.mask, in.nx, in.ny, in.nz, (uint8_t *)p, px, py, pz, (hipStream_t)stream));
+                padded_of[in.mask] = (const uint8_t *)p;
+                in.mask = (const uint8_t *)p;
+            }
+            PM_TRY(wall_scratch.get(4 * (size_t)Np * wall_ue, &p));
+            for (int f = 0; f < 4; ++f) {
+                void *pf = (char *)p + (size_t)f * Np * wall_ue;
+                if (params->warm_start)
+                    PM_HIP(launch_embed(wall_ue, w.user[f], in.nx, in.ny, in.nz, pf, px, py, pz, (hipStream_t)stream));
+                else
+                    PM_HIP(hipMemsetAsync(pf, 0, (size_t)Np * wall_ue, (hipStream_t)stream));
+                in.user[f] = pf;
+            }
+            in.nx = px;
+            in.ny = py;
+            in.nz = pz;
+            in.N = Np;
+            in.no_through_flow = (W >> in.axis) & 1;
+        }
+    }
     // pore cleanup: each instance sweeps a copy of its mask in which the pore
     // components that do not wind along its load axis are solid
     Scratch cleaned(ctx);
@@ -1456,6 +1524,24 @@ pm_status pm_solve_batch(pm_ctx *ctx, void *stream, pm_instance *insts, int32_t 
     {
         Engine eng(ctx, (hipStream_t)stream, params, list);
         rs = eng.run();
+    }
+    if (W && rs == PM_OK) {
+        // back to the caller's grid: fields (solved instances), and the flux and k
+        // as means over the caller's voxels
+        for (size_t i = 0; i < list.size(); ++i) {
+            Inst &in = list[i];
+            const Walled &w = walled[i];
+            if (in.status != PM_ERR_NO_FLOW && w.user[0])
+                for (int f = 0; f < 4; ++f)
+                    PM_HIP(launch_extract(wall_ue, in.user[f], in.nx, in.ny, w.user[f], w.nx, w.ny, w.nz,
+                                          (hipStream_t)stream));
+            const double sc = (double)in.N / (double)w.N;
+            for (int k = 0; k < 3; ++k) in.kcol[k] *= sc;
+            if (in.hist && in.hist->q)
+                for (int64_t j = 0; j < in.hist->n; ++j)
+                    for (int k = 0; k < 3; ++k) in.hist->q[3 * j + k] *= sc;
+        }
+        PM_HIP(hipStreamSynchronize((hipStream_t)stream));
     }
     stats_end(ctx);
     pm_status worst = PM_OK;

@@ -40,6 +40,17 @@ hipError_t launch_counts(const uint8_t *mask, const uint32_t *codes, int64_t n,
 // set faces flagged solid in codes to zero
 hipError_t launch_zero_solid(Prec prec, const uint32_t *codes, int64_t n, void *u, void *v, void *w,
                              hipStream_t s);
+// outer walls: mask padded with solid layers to (px, py, pz) >= (nx, ny, nz); fields
+// embedded into the padded grid (zero in the added layers) or extracted back
+hipError_t launch_pad_mask(const uint8_t *src, int nx, int ny, int nz, uint8_t *dst, int px, int py, int pz,
+                           hipStream_t s);
+hipError_t launch_embed(size_t elem, const void *src, int nx, int ny, int nz, void *dst, int px, int py, int pz,
+                        hipStream_t s);
+hipError_t launch_extract(size_t elem, const void *src, int px, int py, void *dst, int nx, int ny, int nz,
+                          hipStream_t s);
+// mirroring: dst has 2 n_i voxels along every axis i with bit i of axes, the second
+// half the first reflected (dst[2 n_i - 1 - c] = src[c])
+hipError_t launch_mirror(const uint8_t *src, int nx, int ny, int nz, int axes, uint8_t *dst, hipStream_t s);
 // elementwise conversions and copies of n values
 hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream_t s);

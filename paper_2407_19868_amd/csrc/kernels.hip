@@ -172,6 +172,97 @@ hipError_t launch_zero_solid(Prec prec, const uint32_t *codes, int64_t n, void *
     return hipGetLastError();
 }
 
+// ---- outer walls: the grid with solid layers appended along some axes
+
+__global__ void k_pad_mask(const uint8_t *__restrict__ src, int nx, int ny, int nz, uint8_t *__restrict__ dst,
+                           int px, int py, int pz)
+{
+    const int64_t n = (int64_t)px * py * pz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int x = (int)(t % px), y = (int)((t / px) % py), z = (int)(t / ((int64_t)px * py));
+    dst[t] = (x < nx && y < ny && z < nz) ? src[((int64_t)z * ny + y) * nx + x] : (uint8_t)1;
+}
+
+// padded[t] = field at the same (x, y, z) inside the caller's grid, 0 in the added layers
+template <typename T>
+__global__ void k_embed(const T *__restrict__ src, int nx, int ny, int nz, T *__restrict__ dst, int px, int py,
+                        int pz)
+{
+    const int64_t n = (int64_t)px * py * pz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int x = (int)(t % px), y = (int)((t / px) % py), z = (int)(t / ((int64_t)px * py));
+    dst[t] = (x < nx && y < ny && z < nz) ? src[((int64_t)z * ny + y) * nx + x] : T(0);
+}
+
+template <typename T>
+__global__ void k_extract(const T *__restrict__ src, int px, int py, T *__restrict__ dst, int nx, int ny, int nz)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int x = (int)(t % nx), y = (int)((t / nx) % ny), z = (int)(t / ((int64_t)nx * ny));
+    dst[t] = src[((int64_t)z * py + y) * px + x];
+}
+
+hipError_t launch_pad_mask(const uint8_t *src, int nx, int ny, int nz, uint8_t *dst, int px, int py, int pz,
+                           hipStream_t s)
+{
+    const int64_t n = (int64_t)px * py * pz;
+    hipLaunchKernelGGL(k_pad_mask, dim3(grid1d(n, 256)), dim3(256), 0, s, src, nx, ny, nz, dst, px, py, pz);
+    return hipGetLastError();
+}
+
+hipError_t launch_embed(size_t elem, const void *src, int nx, int ny, int nz, void *dst, int px, int py, int pz,
+                        hipStream_t s)
+{
+    const int64_t n = (int64_t)px * py * pz;
+    if (elem == sizeof(double))
+        hipLaunchKernelGGL(k_embed<double>, dim3(grid1d(n, 256)), dim3(256), 0, s, (const double *)src, nx, ny, nz,
+                           (double *)dst, px, py, pz);
+    else
+        hipLaunchKernelGGL(k_embed<float>, dim3(grid1d(n, 256)), dim3(256), 0, s, (const float *)src, nx, ny, nz,
+                           (float *)dst, px, py, pz);
+    return hipGetLastError();
+}
+
+hipError_t launch_extract(size_t elem, const void *src, int px, int py, void *dst, int nx, int ny, int nz,
+                          hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    if (elem == sizeof(double))
+        hipLaunchKernelGGL(k_extract<double>, dim3(grid1d(n, 256)), dim3(256), 0, s, (const double *)src, px, py,
+                           (double *)dst, nx, ny, nz);
+    else
+        hipLaunchKernelGGL(k_extract<float>, dim3(grid1d(n, 256)), dim3(256), 0, s, (const float *)src, px, py,
+                           (float *)dst, nx, ny, nz);
+    return hipGetLastError();
+}
+
+// ---- mirroring: each selected axis doubled by the sample's mirror image
+
+__global__ void k_mirror(const uint8_t *__restrict__ src, int nx, int ny, int nz, int axes, uint8_t *__restrict__ dst,
+                         int mx, int my, int mz)
+{
+    const int64_t n = (int64_t)mx * my * mz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int x = (int)(t % mx), y = (int)((t / mx) % my), z = (int)(t / ((int64_t)mx * my));
+    if ((axes & 1) && x >= nx) x = 2 * nx - 1 - x;
+    if ((axes & 2) && y >= ny) y = 2 * ny - 1 - y;
+    if ((axes & 4) && z >= nz) z = 2 * nz - 1 - z;
+    dst[t] = src[((int64_t)z * ny + y) * nx + x];
+}
+
+hipError_t launch_mirror(const uint8_t *src, int nx, int ny, int nz, int axes, uint8_t *dst, hipStream_t s)
+{
+    const int mx = (axes & 1) ? 2 * nx : nx, my = (axes & 2) ? 2 * ny : ny, mz = (axes & 4) ? 2 * nz : nz;
+    const int64_t n = (int64_t)mx * my * mz;
+    hipLaunchKernelGGL(k_mirror, dim3(grid1d(n, 256)), dim3(256), 0, s, src, nx, ny, nz, axes, dst, mx, my, mz);
+    return hipGetLastError();
+}
+
 hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL((k_convert<double, float>), dim3(grid1d(n, 256)), dim3(256), 0, s, src, dst, n);

@@ -395,3 +395,37 @@ def test_sweep_points_against_assembled_operators():
         w = want[f].reshape(-1)[cells]
         scale = np.abs(want[f]).max()
         assert np.abs(got[:, f] - w).max() / scale < 1e-13
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+def test_outer_walls_channel_closed_form(n):
+    """Outer walls on one axis around n fluid layers, flow along the walls:
+    the plane Poiseuille value with no solid layer inside the sample,
+    k = n^2/12 + 1/24 exactly, and NO_FLOW for a load across the walls."""
+    want = n * n / 12.0 + 1.0 / 24.0
+    prm = oracle.params(tol=1e-11)
+    for wall_axis, flow_axis in [(1, 0), (2, 1), (0, 2)]:
+        shape = [3, 3, 3]
+        shape[2 - wall_axis] = n
+        m = np.zeros(shape, dtype=np.uint8)
+        r = oracle.solve_walls(m, flow_axis, 1 << wall_axis, prm)
+        assert r.status == "OK"
+        assert r.kcol[flow_axis] == pytest.approx(want, rel=1e-9)
+        assert oracle.solve_walls(m, wall_axis, 1 << wall_axis, prm).status == "NO_FLOW"
+
+
+@pytest.mark.parametrize("H, W", [(3, 4), (6, 5)])
+def test_outer_walls_duct_sylvester(H, W):
+    """A duct of H x W fluid voxels whose four sides are outer walls: the
+    discrete equations separate as for the duct with one solid layer around it,
+    now averaged over the H x W cross-section of the sample."""
+    prm = oracle.params(tol=1e-11)
+    nu = 1.0 / prm.re
+    U = scipy.linalg.solve_sylvester(nu * _channel_matrix(H), nu * _channel_matrix(W).T,
+                                     -np.ones((H, W)) * prm.drive)
+    want = U.sum() / (H * W) / (prm.re * prm.drive)
+    m = np.zeros((W, H, 2), dtype=np.uint8)
+    r = oracle.solve_walls(m, 0, 0b110, prm)
+    assert r.status == "OK"
+    assert r.kcol[0] == pytest.approx(want, rel=1e-9)
+    assert r.state.u.shape == m.shape
