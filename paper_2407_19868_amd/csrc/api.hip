@@ -272,7 +272,10 @@ int auto_zc(int nx, int ny, int nz, int tx, int ty)
     // aim for >= 512 workgroups (two 8-wave groups per CU) while keeping chunks
     // long enough to amortise priming the z window (7 extra planes of u and v)
     int64_t zc = (int64_t)nz * txy * tx * ty / (512LL * 512LL);
-    zc = std::max<int64_t>(16, std::min<int64_t>(64, zc));
+    // small grids cannot fill the chip even with 16-plane chunks: there the sweep
+    // is latency-bound (one plane after another per workgroup), so shorter chunks
+    // and more workgroups win and the priming bytes do not matter
+    zc = zc < 16 ? std::max<int64_t>(4, zc) : std::min<int64_t>(64, zc);
     return (int)std::min<int64_t>(zc, nz);
 }
 
