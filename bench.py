@@ -214,7 +214,7 @@ def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--sweeps-per-step", type=int, default=500)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="form of the main line; the other form is reported beside it")

@@ -298,8 +298,11 @@ hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream
 // its own cell and of its -x and -y neighbours (the pressure gradient of a
 // face reads the cell behind it), so pressures are never exchanged.  LDS
 // slots rotate (u, v, p over 2 planes, w over 3), which leaves one barrier
-// per plane, and every global load -- own column and halo -- is issued two
-// planes before it is needed (HBM latency spans more than one plane's work).
+// per plane.  Every global load -- own column and halo -- is issued one
+// iteration before the plane it feeds is staged, behind the barrier and the
+// arithmetic of the current plane (with 4-7 waves per SIMD that covers the
+// HBM latency; loading two iterations ahead measured no faster and held 25
+// more registers).
 // Results and stencil codes are touched once per launch: their stores and
 // loads are non-temporal, leaving L2 to the planes that neighbouring tiles
 // read again as halo.
@@ -409,8 +412,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
         has_ph = (px == 1 && py >= 2 && py <= TY + 1) || (py == 1 && px >= 2 && px <= TX + 1);
     }
 
-    // ---- prime the registers for the prologue plane zz = z0 - 1 and the
-    // loads of plane z0 (loads run two planes ahead of their use)
+    // ---- prime the registers for the prologue plane zz = z0 - 1
     T Uw[5], Vw[5], Ww[3];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
@@ -424,7 +426,6 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
     int z1p = wrap_int(z0, nz);       // zz + 1
     int z2p = wrap_int(z0 + 1, nz);   // zz + 2
     int z3p = wrap_int(z0 + 2, nz);   // zz + 3
-    int z4p = wrap_int(z0 + 3, nz);   // zz + 4
     T pold = Pin[(int64_t)zcur * plane + own];
     uint32_t code = 0;
     T hU = T(0), hV = T(0), hW = T(0), hP = T(0);
@@ -433,19 +434,6 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
         hV = Vin[(int64_t)zcur * plane + hoff];
         hW = Win[(int64_t)z1p * plane + hoff];
         if (has_ph) hP = Pin[(int64_t)zcur * plane + hoff];
-    }
-    // values for iteration zz + 1
-    T aU = Uin[(int64_t)z3p * plane + own];
-    T aV = Vin[(int64_t)z3p * plane + own];
-    T aW = Win[(int64_t)z2p * plane + own];
-    T aP = Pin[(int64_t)z1p * plane + own];
-    uint32_t aC = __builtin_nontemporal_load(&codes[(int64_t)z1p * plane + own]);
-    T ahU = T(0), ahV = T(0), ahW = T(0), ahP = T(0);
-    if (has_halo) {
-        ahU = Uin[(int64_t)z1p * plane + hoff];
-        ahV = Vin[(int64_t)z1p * plane + hoff];
-        ahW = Win[(int64_t)z2p * plane + hoff];
-        if (has_ph) ahP = Pin[(int64_t)z1p * plane + hoff];
     }
     int slot = 0;                   // u, v, p slot of plane zz
     int wc = 0, wn = 1;             // w slots of planes zz and zz + 1
@@ -473,24 +461,24 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
             if (has_ph) sp[hlds] = hP;
         }
 
-        // ---- loads for iteration zz + 2 (planes wrap, so every address is
-        // valid); the last two iterations of the chunk need none
-        const bool ahead = zz + 2 < z1;
+        // ---- loads for iteration zz + 1 (planes wrap, so every address is
+        // valid); the last iteration of the chunk needs none
+        const bool ahead = zz + 1 < z1;
         T bU = T(0), bV = T(0), bW = T(0), bP = T(0);
         uint32_t bC = 0;
         if (ahead) {
-            bU = Uin[(int64_t)z4p * plane + own];
-            bV = Vin[(int64_t)z4p * plane + own];
-            bW = Win[(int64_t)z3p * plane + own];
-            bP = Pin[(int64_t)z2p * plane + own];
-            bC = __builtin_nontemporal_load(&codes[(int64_t)z2p * plane + own]);
+            bU = Uin[(int64_t)z3p * plane + own];
+            bV = Vin[(int64_t)z3p * plane + own];
+            bW = Win[(int64_t)z2p * plane + own];
+            bP = Pin[(int64_t)z1p * plane + own];
+            bC = __builtin_nontemporal_load(&codes[(int64_t)z1p * plane + own]);
         }
         T bhU = T(0), bhV = T(0), bhW = T(0), bhP = T(0);
         if (has_halo && ahead) {
-            bhU = Uin[(int64_t)z2p * plane + hoff];
-            bhV = Vin[(int64_t)z2p * plane + hoff];
-            bhW = Win[(int64_t)z3p * plane + hoff];
-            if (has_ph) bhP = Pin[(int64_t)z2p * plane + hoff];
+            bhU = Uin[(int64_t)z1p * plane + hoff];
+            bhV = Vin[(int64_t)z1p * plane + hoff];
+            bhW = Win[(int64_t)z2p * plane + hoff];
+            if (has_ph) bhP = Pin[(int64_t)z1p * plane + hoff];
         }
         __syncthreads();
 
@@ -553,31 +541,21 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
             Uw[j] = Uw[j + 1];
             Vw[j] = Vw[j + 1];
         }
-        Uw[4] = aU;
-        Vw[4] = aV;
+        Uw[4] = bU;
+        Vw[4] = bV;
         Ww[0] = Ww[1];
         Ww[1] = Ww[2];
-        Ww[2] = aW;
-        pold = aP;
-        code = aC;
-        hU = ahU;
-        hV = ahV;
-        hW = ahW;
-        hP = ahP;
-        aU = bU;
-        aV = bV;
-        aW = bW;
-        aP = bP;
-        aC = bC;
-        ahU = bhU;
-        ahV = bhV;
-        ahW = bhW;
-        ahP = bhP;
+        Ww[2] = bW;
+        pold = bP;
+        code = bC;
+        hU = bhU;
+        hV = bhV;
+        hW = bhW;
+        hP = bhP;
         zcur = z1p;
         z1p = z2p;
         z2p = z3p;
-        z3p = z4p;
-        z4p = (z4p + 1 == nz) ? 0 : z4p + 1;
+        z3p = (z3p + 1 == nz) ? 0 : z3p + 1;
         slot ^= 1;
         wc = wn;
         wn = (wn == 2) ? 0 : wn + 1;
