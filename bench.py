@@ -145,13 +145,37 @@ def series_workload(args) -> dict:
             log(f"[bench] 1536^3 {form}: {gv:.1f} GVox/s ({100 * res[form]['hbm_frac']:.1f}% HBM)")
             del f
             torch.cuda.empty_cache()
+        decay = None
+        if args.decay_sweeps > 0:
+            # residual history of a FP32 solve along x from rest; the tail's geometric
+            # decay rate per sweep extrapolates the sweeps to r < 1e-8
+            log(f"[bench] 1536^3 residual decay over {args.decay_sweeps} sweeps (FP32)")
+            f = [torch.zeros(mask_np.shape, dtype=torch.float32, device="cuda") for _ in range(4)]
+            t0 = time.perf_counter()
+            r = ctx.solve(mask, 0, ps.params(precision=ps.FP32, max_sweeps=args.decay_sweeps, tol=1e-12,
+                                             progress=10), fields=f)
+            wall = time.perf_counter() - t0
+            sw, rr = r.hist_sweep.astype(float), r.hist_r
+            tail = sw >= sw[-1] / 2
+            rate = float(-np.polyfit(sw[tail], np.log(rr[tail]), 1)[0])  # e-folds per sweep
+            more = np.log(rr[-1] / 1e-8) / rate if rate > 0 else float("inf")
+            decay = {"sweeps": int(r.sweeps), "seconds": round(wall, 1), "r_last": float(rr[-1]),
+                     "efolds_per_1000_sweeps": round(1000 * rate, 4),
+                     "extrapolated_sweeps_to_1e-8": int(r.sweeps + more),
+                     "extrapolated_hours_per_axis_fp32": round((r.sweeps + more) * N / (res["fp32"]["gvox_per_s_kernel"] * 1e9) / 3600, 2),
+                     "method": "least-squares fit of log r against sweeps over the second half of the history; "
+                               "geometric decay assumed from there to r = 1e-8 at the measured FP32 rate",
+                     "k_col_at_end": [float(f"{x:.8g}") for x in r.kcol]}
+            log(f"[bench] decay: r {rr[-1]:.3e} after {r.sweeps} sweeps, {1000 * rate:.3f} e-folds/1000 sweeps")
+            del f
+            torch.cuda.empty_cache()
         ctx.close()
         return {"metric": "GVoxel-updates/s per sweep (% HBM roofline)", "value": res["fp32"]["gvox_per_s_kernel"],
                 "unit": "GVoxel-updates/s", "dtype": "f32", "data": "synthetic",
                 "config": {"workload": "overlapping spheres 1536^3, radius U[5,12], porosity 0.20, seed 5; "
                                        "load axis x; fields from rest",
                            "grid": [1536, 1536, 1536], "porosity": round(float(1 - mask_np.mean()), 4)},
-                "forms": res}
+                "forms": res, "residual_decay": decay}
 
     if args.workload == "precipitation":
         log("[bench] generating the precipitation series (16 states, 1024x512x16 + walls)")
@@ -198,6 +222,25 @@ def series_workload(args) -> dict:
              "sweeps": r["sweeps"], "r_last": float(r["r"][-1]) if len(r["r"]) else None,
              "k_col": [float(f"{x:.8g}") for x in r["kcol"]]} for i, r in enumerate(res)]
     log(f"[bench] {args.workload}: {wall:.2f} s for {len(res)} instances, status {status}")
+    seq = None
+    if args.compare_sweeps > 0:
+        # the same instances for a fixed number of sweeps: one batched solve against
+        # one solve per instance, one after the other
+        cmp_prm = ps.params(precision=ps.FP32_DC, max_sweeps=args.compare_sweeps, tol=1e-30,
+                            pore_cleanup=args.pore_cleanup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.solve_batch(probs, cmp_prm)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for m, a in probs:
+            ctx.solve(m, a, cmp_prm)
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        seq = {"sweeps_each": args.compare_sweeps, "batched_s": round(t_batch, 3), "sequential_s": round(t_seq, 3),
+               "speedup": round(t_seq / t_batch, 3)}
+        log(f"[bench] {args.compare_sweeps} sweeps each: batched {t_batch:.2f} s, sequential {t_seq:.2f} s")
     ctx.close()
     return {"metric": "time-to-all-k-columns (batched series, FP32 fields + FP64 defect correction)",
             "value": round(wall, 3), "unit": "s", "higher_is_better": False, "dtype": "f32+f64",
@@ -206,7 +249,7 @@ def series_workload(args) -> dict:
             "sweep_kernel_ms": round(st["sweep_ms"], 1),
             "config": {"workload": desc, "instances": len(res), "max_sweeps": args.max_sweeps,
                        "pore_cleanup": args.pore_cleanup},
-            "pore_connectivity_s": round(pores_s, 3), "pores": pore_info,
+            "pore_connectivity_s": round(pores_s, 3), "pores": pore_info, "batched_vs_sequential": seq,
             "instances": inst}
 
 
@@ -230,6 +273,10 @@ def main() -> int:
                          "batched series and the large single domain")
     ap.add_argument("--max-sweeps", type=int, default=200000,
                     help="sweep budget of the series solves (--workload precipitation/foam)")
+    ap.add_argument("--compare-sweeps", type=int, default=0,
+                    help="series workloads: also time this many sweeps per instance batched vs sequential")
+    ap.add_argument("--decay-sweeps", type=int, default=0,
+                    help="spheres1536: FP32 solve of this many sweeps to extrapolate the sweeps to r < 1e-8")
     ap.add_argument("--pore-cleanup", type=int, choices=[0, 1], default=0,
                     help="series workloads: sweep only the pore components that percolate along the load axis")
     ap.add_argument("--calibrate-copy", action="store_true",
