@@ -107,6 +107,14 @@ def cpu_baseline(mask, seconds: float):
                       f"({dt:.1f} s)"}
 
 
+def tile_override(args) -> dict:
+    """--tile TXxTYxZC as solver parameters (empty: the library's own choice)."""
+    if not args.tile:
+        return {}
+    tx, ty, zc = (int(v) for v in args.tile.split("x"))
+    return {"tile_x": tx, "tile_y": ty, "zchunk": zc}
+
+
 def series_workload(args) -> dict:
     """Batched series (one launch per sweep over every instance, each stopping on
     its own) and the large single domain."""
@@ -126,10 +134,11 @@ def series_workload(args) -> dict:
         for form, prec in (("fp32", ps.FP32), ("fp64", ps.FP64)):
             dt = torch.float32 if prec == ps.FP32 else torch.float64
             f = [torch.zeros(mask_np.shape, dtype=dt, device="cuda") for _ in range(4)]
-            ctx.iterate(mask, 0, f, 2, ps.params(precision=prec))
+            prm = ps.params(precision=prec, **tile_override(args))
+            ctx.iterate(mask, 0, f, 2, prm)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            ctx.iterate(mask, 0, f, args.sweeps_per_step // 5, ps.params(precision=prec))
+            ctx.iterate(mask, 0, f, args.sweeps_per_step // 5, prm)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
             st = ctx.last_stats()
@@ -266,7 +275,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=40.0,
                     help="target of the oracle sample (the calibration undershoots: ~10-20 s result)")
-    ap.add_argument("--tile", default="", help="TXxTYxZC override, e.g. 64x8x32")
+    ap.add_argument("--tile", default="", help="TXxTYxZC override, e.g. 64x8x32 (ZC 0: automatic)")
     ap.add_argument("--workload", default="spheres256",
                     choices=["spheres256", "precipitation", "foam", "spheres1536"],
                     help="spheres256: the throughput line (default); the others report the "
@@ -311,10 +320,7 @@ def main() -> int:
         mask_np = synth.spheres(n, n, n, 6.0, 10.0, 0.35, 2)
     mask = ps.to_device(mask_np)
     ctx = ps.Context(0)
-    tile = {}
-    if args.tile:
-        tx, ty, zc = (int(v) for v in args.tile.split("x"))
-        tile = {"tile_x": tx, "tile_y": ty, "zchunk": zc}
+    tile = tile_override(args)
     N = mask_np.size
 
     def measure(form: str):

@@ -89,8 +89,8 @@ typedef struct {
                            between checks, the paper's criterion §7.1)              */
     int32_t warm_start; /* 1: start from the fields passed in (else from rest)       */
     int32_t kernel;     /* pm_kernel.                           default AUTO         */
-    int32_t tile_x;     /* fused-kernel tile override (0 = auto): 32 or 64           */
-    int32_t tile_y;     /* fused-kernel tile override (0 = auto): 4, 8 or 16         */
+    int32_t tile_x;     /* fused-kernel tile override (0 = auto); (tile_x, tile_y)   */
+    int32_t tile_y;     /* one of 128x8, 64x8, 64x16, 32x8, 32x16                   */
     int32_t zchunk;     /* planes per workgroup along z (0 = auto)                   */
     int32_t graphs;     /* 1: each block of check_every sweeps (plus its reduction
                            and copy-back) is captured once as a HIP graph and
@@ -151,10 +151,20 @@ pm_status pm_create(int hip_device, size_t mem_cap_bytes, pm_ctx **out);
 /* Free the context and its device scratch.  NULL is ignored. */
 void pm_destroy(pm_ctx *ctx);
 
+/* Device memory the library allocates for a call (stencil codes, the second
+ * field set, partial sums) is not freed when the call returns: the context
+ * keeps it for reuse by later calls, so that repeated solves of one size do
+ * not map and unmap pages each time.  A request takes a kept block when one
+ * is at most 1/8 larger.  Kept blocks count against mem_cap_bytes and are
+ * returned to the device when an allocation would exceed the cap or fails,
+ * by pm_trim, and by pm_destroy.  pm_trim returns them now (PM_ERR_ARG for a
+ * NULL context). */
+pm_status pm_trim(pm_ctx *ctx);
+
 /* Message of the last error on this context ("" if none).  Valid until the next call. */
 const char *pm_last_error(const pm_ctx *ctx);
 
-/* Device bytes currently held by the context. */
+/* Device bytes currently held by the context, kept blocks included. */
 size_t pm_mem_used(const pm_ctx *ctx);
 
 /*
@@ -275,8 +285,9 @@ typedef struct {
     double total_ms;         /* host wall time of the call                             */
     int32_t tile_x, tile_y, zchunk;  /* decomposition of the last instance             */
     int32_t precision;       /* pm_precision of the last sweep launch (PM_FP64/PM_FP32) */
-    int64_t peak_bytes;      /* most device memory the library held during the call
-                                (its own allocations, not the caller's buffers)          */
+    int64_t peak_bytes;      /* most device memory the call had in use at once (the
+                                library's own allocations, not the caller's buffers,
+                                not blocks kept idle for later calls)                    */
 } pm_stats;
 
 /* Copy the statistics of the last call into *out (host). */

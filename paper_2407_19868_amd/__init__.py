@@ -30,7 +30,7 @@ KERNEL_AUTO, KERNEL_FUSED, KERNEL_SIMPLE = 0, 1, 2
 EXPORTS = ("pm_params_default", "pm_status_string", "pm_create", "pm_destroy", "pm_last_error",
            "pm_mem_used", "pm_preprocess", "pm_face_codes", "pm_iterate", "pm_residual", "pm_solve",
            "pm_tensor", "pm_solve_batch", "pm_last_stats", "pm_autotune", "pm_principal_axes",
-           "pm_plane_angle", "pm_pores", "pm_mirror")
+           "pm_plane_angle", "pm_pores", "pm_mirror", "pm_trim")
 ISOTROPIC, TRANSVERSE, ORTHOTROPIC = 0, 1, 2
 CLASS_NAMES = {ISOTROPIC: "isotropic", TRANSVERSE: "transverse", ORTHOTROPIC: "orthotropic"}
 
@@ -155,6 +155,8 @@ def load_library(path: str = LIB_PATH):
     lib.pm_last_error.restype = ctypes.c_char_p
     lib.pm_mem_used.argtypes = [vp]
     lib.pm_mem_used.restype = ctypes.c_size_t
+    lib.pm_trim.argtypes = [vp]
+    lib.pm_trim.restype = i32
     lib.pm_preprocess.argtypes = [vp, vp, vp, i64, i64, i64, vp]
     lib.pm_preprocess.restype = i32
     lib.pm_face_codes.argtypes = [vp, vp, vp, i64, i64, i64, vp]
@@ -297,7 +299,12 @@ class Context:
         return self._lib.pm_last_error(self._h).decode()
 
     def mem_used(self) -> int:
+        """Device bytes the context holds, blocks kept for reuse included."""
         return int(self._lib.pm_mem_used(self._h))
+
+    def trim(self) -> None:
+        """Return the device blocks kept for reuse between calls."""
+        self._check(self._lib.pm_trim(self._h))
 
     def autotune(self, mask, precision: int = FP64) -> tuple:
         """Time the fused-kernel decompositions on this mask; returns (tile_x, tile_y, zchunk)."""

@@ -23,7 +23,9 @@ using namespace ps;
 
 struct pm_ctx {
     int dev = 0;
-    size_t cap = 0, used = 0;
+    size_t cap = 0, used = 0;  // used: bytes in use by the running call
+    size_t pooled = 0;         // bytes kept for reuse between calls
+    std::multimap<size_t, void *> pool;
     std::string err;
     std::unordered_map<void *, size_t> allocs;
     double *h_sums = nullptr;  // pinned host buffer for reduced sums
@@ -63,18 +65,45 @@ pm_status fail(pm_ctx *ctx, pm_status s, const char *fmt, ...)
         if (s_ != PM_OK) return s_;                                                                    \
     } while (0)
 
+void release_pool(pm_ctx *ctx)
+{
+    for (auto &kv : ctx->pool) (void)hipFree(kv.second);
+    ctx->pool.clear();
+    ctx->pooled = 0;
+}
+
+// Device memory of a call.  Blocks that earlier calls released stay with the
+// context and are handed out again when a request fits one within 1/8 of its
+// size: repeated solves then skip hipMalloc (page mapping) and hipFree (a
+// device-wide wait).  The pool goes back to the device when the cap or the
+// device runs short, on pm_trim and on pm_destroy.
 pm_status dalloc(pm_ctx *ctx, size_t bytes, void **out)
 {
     *out = nullptr;
     if (bytes == 0) bytes = 256;
-    if (ctx->cap && ctx->used + bytes > ctx->cap)
-        return fail(ctx, PM_ERR_OOM, "device allocation of %zu bytes exceeds the context cap (%zu used of %zu)",
-                    bytes, ctx->used, ctx->cap);
-    hipError_t e = hipMalloc(out, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        *out = nullptr;
-        return fail(ctx, PM_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    auto hit = ctx->pool.lower_bound(bytes);
+    if (hit != ctx->pool.end() && hit->first - bytes <= bytes / 8) {
+        const size_t got = hit->first;
+        *out = hit->second;
+        ctx->pool.erase(hit);
+        ctx->pooled -= got;
+        bytes = got;
+    } else {
+        if (ctx->cap && ctx->used + ctx->pooled + bytes > ctx->cap) release_pool(ctx);
+        if (ctx->cap && ctx->used + bytes > ctx->cap)
+            return fail(ctx, PM_ERR_OOM, "device allocation of %zu bytes exceeds the context cap (%zu used of %zu)",
+                        bytes, ctx->used, ctx->cap);
+        hipError_t e = hipMalloc(out, bytes);
+        if (e != hipSuccess && ctx->pooled) {
+            (void)hipGetLastError();
+            release_pool(ctx);
+            e = hipMalloc(out, bytes);
+        }
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            *out = nullptr;
+            return fail(ctx, PM_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        }
     }
     ctx->allocs[*out] = bytes;
     ctx->used += bytes;
@@ -82,15 +111,17 @@ pm_status dalloc(pm_ctx *ctx, size_t bytes, void **out)
     return PM_OK;
 }
 
+// Return a block of dalloc to the pool.  The caller has finished every
+// kernel and copy that uses it.
 void dfree(pm_ctx *ctx, void *p)
 {
     if (!p) return;
     auto it = ctx->allocs.find(p);
-    if (it != ctx->allocs.end()) {
-        ctx->used -= it->second;
-        ctx->allocs.erase(it);
-    }
-    (void)hipFree(p);
+    if (it == ctx->allocs.end()) return;
+    ctx->used -= it->second;
+    ctx->pool.emplace(it->second, p);
+    ctx->pooled += it->second;
+    ctx->allocs.erase(it);
 }
 
 // Device allocations owned by one call, released on every exit path.
@@ -100,6 +131,11 @@ struct Scratch {
     explicit Scratch(pm_ctx *c) : ctx(c) {}
     ~Scratch()
     {
+        if (ptrs.empty()) return;
+        // an error return may leave work queued that reads these blocks: let
+        // it finish before another call can be handed them
+        (void)hipDeviceSynchronize();
+        (void)hipGetLastError();
         for (void *p : ptrs) dfree(ctx, p);
     }
     pm_status get(size_t bytes, void **out)
@@ -288,9 +324,19 @@ TileCfg pick_tiles(pm_ctx *ctx, const pm_params *prm, int nx, int ny, int nz, Pr
         c.ty = it->second[1];
         c.zc = it->second[2];
     } else {
-        // measured defaults on MI355X (256^3 packing): FP64 64x8, FP32 64x16
+        // Measured on MI355X (256^3 packing, three instances per launch):
+        // FP64 64x8 (two 8-wave workgroups per CU, so one group's per-plane
+        // barrier overlaps the other's work; 128x8 reads 15 % fewer bytes but
+        // runs alone on its CU and is 1 % slower).  FP32 128x8 (2 % faster
+        // than 64x16), unless 128-wide tiles pad x more than 64-wide ones
+        // (nx = 150: 256 against 192 columns).
+        const int64_t pad128 = (nx + 127) / 128 * 128, pad64 = (nx + 63) / 64 * 64;
         c.tx = 64;
-        c.ty = prec == kF64 ? 8 : 16;
+        c.ty = 8;
+        if (prec != kF64) {
+            c.tx = pad128 <= pad64 ? 128 : 64;
+            c.ty = pad128 <= pad64 ? 8 : 16;
+        }
         c.zc = 0;
     }
     if (prm->tile_x && prm->tile_y) {
@@ -857,7 +903,7 @@ pm_status autotune_shape(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx
     PM_TRY(scratch.get(2 * sizeof(InstDev), &tab));
     PM_HIP(launch_face_codes(mask, nx, ny, nz, (uint32_t *)codes, s));
     PM_HIP(hipMemsetAsync(fields, 0, 4 * (size_t)N * elem(prec), s));
-    const int tiles[4][2] = {{64, 8}, {32, 8}, {32, 16}, {64, 16}};
+    const int tiles[5][2] = {{128, 8}, {64, 8}, {32, 8}, {32, 16}, {64, 16}};
     const int zcs[4] = {16, 32, 64, 128};
     std::vector<TileCfg> cands;
     for (auto &t : tiles) {
@@ -1227,13 +1273,23 @@ void pm_destroy(pm_ctx *ctx)
     for (int i = 0; i < 2; ++i)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     for (auto &kv : ctx->allocs) (void)hipFree(kv.first);
+    release_pool(ctx);
     if (ctx->h_sums) (void)hipHostFree(ctx->h_sums);
     delete ctx;
 }
 
 const char *pm_last_error(const pm_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-size_t pm_mem_used(const pm_ctx *ctx) { return ctx ? ctx->used : 0; }
+size_t pm_mem_used(const pm_ctx *ctx) { return ctx ? ctx->used + ctx->pooled : 0; }
+
+pm_status pm_trim(pm_ctx *ctx)
+{
+    if (!ctx) return PM_ERR_ARG;
+    ctx->err.clear();
+    PM_TRY(set_device(ctx));
+    release_pool(ctx);
+    return PM_OK;
+}
 
 pm_status pm_preprocess(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz,
                         uint32_t *bits)

@@ -307,6 +307,29 @@ hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream
 // loads are non-temporal, leaving L2 to the planes that neighbouring tiles
 // read again as halo.
 
+// The far-wall coefficient of App. B (-1/5, on v[+2] when the near wall is
+// at -1, on v[-2] when it is at +1) is nonzero for exactly two codes, so the
+// LDS table holds (a, b) only -- one 16-byte read per lookup in FP64 instead
+// of two -- and gp, gm come from two compares.  Same values, same operation
+// order as d2_perp: the result is bitwise the same.
+template <typename T>
+struct CoefAB {
+    T a, b;
+};
+
+template <typename T>
+__device__ __forceinline__ T d2_perp_tab(const CoefAB<T> *tab, uint32_t c, T vm2, T vm1, T v0, T vp1, T vp2)
+{
+    const CoefAB<T> ab = tab[c];
+    const T far = -(T(1) / T(5));
+    const T gp = c == 1u ? far : T(0);
+    const T gm = c == 2u ? far : T(0);
+    T t = gm * vm2;
+    t = fma(gp, vp2, t);
+    t = fma(ab.b, v0, t);
+    return fma(ab.a, vm1 + vp1, t);
+}
+
 // MI355X: 8 XCDs of 32 CUs; workgroup i of a dispatch goes to XCD i mod 8.
 constexpr int kNumXcd = 8;
 
@@ -317,7 +340,7 @@ struct FusedShared {
     T v[2][PP];
     T p[2][PP];
     T w[3][PP];
-    Coef<T> tab[8];
+    CoefAB<T> tab[8];
     double red[kNumSums * (TX * TY / 64)];
 };
 
@@ -380,7 +403,10 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    if (tid < 8) sh.tab[tid] = coef_of_code<T>(tid);
+    if (tid < 8) {
+        const Coef<T> c8 = coef_of_code<T>(tid);
+        sh.tab[tid] = {c8.a, c8.b};
+    }
 
     // ---- own column (inactive threads hold the wrapped column: LDS stays periodic)
     const int gx = x0 + tx, gy = y0 + ty;
@@ -498,25 +524,25 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
             const uint32_t cu = code;
             const T u0 = Uw[2];
             const T u_d2x = d2_own(su[cl - 1], u0, su[cl + 1]);
-            const T u_d2y = d2_perp(sh.tab[cu & 7], su[cl - 2 * PX], su[cl - PX], u0, su[cl + PX], su[cl + 2 * PX]);
-            const T u_d2z = d2_perp(sh.tab[(cu >> 3) & 7], Uw[0], Uw[1], u0, Uw[3], Uw[4]);
+            const T u_d2y = d2_perp_tab(sh.tab, cu & 7, su[cl - 2 * PX], su[cl - PX], u0, su[cl + PX], su[cl + 2 * PX]);
+            const T u_d2z = d2_perp_tab(sh.tab, (cu >> 3) & 7, Uw[0], Uw[1], u0, Uw[3], Uw[4]);
             const T Fu = momentum(u_d2x, u_d2y, u_d2z, pn, pxm, nu, gu);
             const bool su_ = (cu & kSolidBit) != 0;
             __builtin_nontemporal_store(su_ ? T(0) : fma(dt, Fu, u0), &Uout[o]);
             // v: own axis y, across x (LDS) and z (registers)
             const uint32_t cv = code >> kCodeBits;
             const T v0 = Vw[2];
-            const T v_d2x = d2_perp(sh.tab[cv & 7], sv[cl - 2], sv[cl - 1], v0, sv[cl + 1], sv[cl + 2]);
+            const T v_d2x = d2_perp_tab(sh.tab, cv & 7, sv[cl - 2], sv[cl - 1], v0, sv[cl + 1], sv[cl + 2]);
             const T v_d2y = d2_own(sv[cl - PX], v0, sv[cl + PX]);
-            const T v_d2z = d2_perp(sh.tab[(cv >> 3) & 7], Vw[0], Vw[1], v0, Vw[3], Vw[4]);
+            const T v_d2z = d2_perp_tab(sh.tab, (cv >> 3) & 7, Vw[0], Vw[1], v0, Vw[3], Vw[4]);
             const T Fv = momentum(v_d2x, v_d2y, v_d2z, pn, pym, nu, gv);
             const bool sv_ = (cv & kSolidBit) != 0;
             __builtin_nontemporal_store(sv_ ? T(0) : fma(dt, Fv, v0), &Vout[o]);
             // w: own axis z (registers), across x and y (LDS)
             const uint32_t cw = code >> (2 * kCodeBits);
             const T w0 = Ww[1];
-            const T w_d2x = d2_perp(sh.tab[cw & 7], swc[cl - 2], swc[cl - 1], w0, swc[cl + 1], swc[cl + 2]);
-            const T w_d2y = d2_perp(sh.tab[(cw >> 3) & 7], swc[cl - 2 * PX], swc[cl - PX], w0, swc[cl + PX],
+            const T w_d2x = d2_perp_tab(sh.tab, cw & 7, swc[cl - 2], swc[cl - 1], w0, swc[cl + 1], swc[cl + 2]);
+            const T w_d2y = d2_perp_tab(sh.tab, (cw >> 3) & 7, swc[cl - 2 * PX], swc[cl - PX], w0, swc[cl + PX],
                                     swc[cl + 2 * PX]);
             const T w_d2z = d2_own(Ww[0], w0, Ww[2]);
             const T Fw = momentum(w_d2x, w_d2y, w_d2z, pn, pn_prev, nu, gw);
@@ -568,7 +594,7 @@ bool fused_tile_supported(int tx, int ty, int prec)
     // one halo position per thread; LDS rings within a workgroup's 160 KiB
     // (64x16 in FP64 takes 98 KiB: one workgroup of 16 waves per CU)
     (void)prec;
-    return (tx == 64 && (ty == 8 || ty == 16)) || (tx == 32 && (ty == 8 || ty == 16));
+    return (tx == 128 && ty == 8) || (tx == 64 && (ty == 8 || ty == 16)) || (tx == 32 && (ty == 8 || ty == 16));
 }
 
 template <typename T>
@@ -586,6 +612,7 @@ static hipError_t launch_fused_t(int tx, int ty, const InstDev *insts, int ninst
                                parity);                                                                    \
         return hipGetLastError();                                                                          \
     }
+    PS_FUSED_CASE(128, 8)
     PS_FUSED_CASE(64, 8)
     PS_FUSED_CASE(64, 16)
     PS_FUSED_CASE(32, 8)

@@ -115,7 +115,8 @@ def test_iterate_fp64_against_oracle(ctx, name, count):
         assert np.abs(g - w).max() / scale <= 1e-12
 
 
-TILES = [(64, 8, 0), (64, 8, 3), (32, 16, 1), (32, 8, 5), (32, 16, 2), (64, 8, 64), (64, 16, 1), (64, 16, 0)]
+TILES = [(64, 8, 0), (64, 8, 3), (32, 16, 1), (32, 8, 5), (32, 16, 2), (64, 8, 64), (64, 16, 1), (64, 16, 0),
+         (128, 8, 0), (128, 8, 2)]
 TILES_F32 = []
 
 
@@ -270,6 +271,43 @@ def test_memory_cap(ctx):
             small.solve(m, 0)
 
 
+def test_kept_blocks_are_reused_and_trimmed():
+    """Blocks released by one call serve the next call of the same size (held
+    memory does not grow, results are identical); pm_trim returns them."""
+    m = ps.to_device(synth.spheres(24, 20, 18, 2.0, 3.0, 0.5, 3))
+    with ps.Context(0) as c:
+        assert c.mem_used() == 0
+        a = c.solve(m, 0)
+        held = c.mem_used()
+        assert held >= c.last_stats()["peak_bytes"] > 0
+        b = c.solve(m, 0)
+        assert c.mem_used() == held
+        assert a.sweeps == b.sweeps and np.array_equal(a.kcol, b.kcol)
+        c.trim()
+        assert c.mem_used() == 0
+        d = c.solve(m, 0)
+        assert np.array_equal(a.kcol, d.kcol)
+
+
+def test_kept_blocks_yield_to_the_cap():
+    """Under a cap that fits either of two problems but not both, the blocks kept
+    from the first are returned when the second needs room."""
+    ma = ps.to_device(synth.spheres(32, 32, 32, 2.0, 3.0, 0.5, 4))
+    mb = ps.to_device(synth.spheres(40, 36, 28, 2.0, 3.0, 0.5, 5))
+    with ps.Context(0) as c:
+        ra = c.solve(ma, 0, ps.params(max_sweeps=200))
+        pa = c.last_stats()["peak_bytes"]
+        rb = c.solve(mb, 0, ps.params(max_sweeps=200))
+        pb = c.last_stats()["peak_bytes"]
+    cap = max(pa, pb) + 4096
+    assert cap < pa + pb
+    with ps.Context(0, mem_cap=cap) as c:
+        for m, want in ((ma, ra), (mb, rb), (ma, ra)):
+            got = c.solve(m, 0, ps.params(max_sweeps=200))
+            assert np.array_equal(got.kcol, want.kcol)
+            assert c.mem_used() <= cap
+
+
 # ------------------------------------------------------------ graphs, tuning, precision forms
 
 def test_graph_replay_equals_direct_launches(ctx):
@@ -292,7 +330,7 @@ def test_autotune_choice_is_supported_and_exact(prec):
     with ps.Context(0) as c:
         ref = c.solve(m, 0, ps.params(precision=prec, max_sweeps=300))
         best = c.autotune(m, prec)
-        assert best[0] in (32, 64) and best[1] in (8, 16) and 1 <= best[2] <= 30
+        assert tuple(best[:2]) in {(128, 8), (64, 8), (64, 16), (32, 8), (32, 16)} and 1 <= best[2] <= 30
         tuned = c.solve(m, 0, ps.params(precision=prec, max_sweeps=300))
         assert c.last_stats()["tile_x"] == best[0] and c.last_stats()["zchunk"] == best[2]
         # the iterate is bitwise identical; sums over another block decomposition
