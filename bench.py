@@ -133,7 +133,7 @@ def series_workload(args) -> dict:
         res = {}
         for form, prec in (("fp32", ps.FP32), ("fp64", ps.FP64)):
             dt = torch.float32 if prec == ps.FP32 else torch.float64
-            f = [torch.zeros(mask_np.shape, dtype=dt, device="cuda") for _ in range(4)]
+            f = list(ps.field_set(mask_np.shape, dt))
             prm = ps.params(precision=prec, **tile_override(args))
             ctx.iterate(mask, 0, f, 2, prm)
             torch.cuda.synchronize()
@@ -159,7 +159,7 @@ def series_workload(args) -> dict:
             # residual history of a FP32 solve along x from rest; the tail's geometric
             # decay rate per sweep extrapolates the sweeps to r < 1e-8
             log(f"[bench] 1536^3 residual decay over {args.decay_sweeps} sweeps (FP32)")
-            f = [torch.zeros(mask_np.shape, dtype=torch.float32, device="cuda") for _ in range(4)]
+            f = list(ps.field_set(mask_np.shape, torch.float32))
             t0 = time.perf_counter()
             r = ctx.solve(mask, 0, ps.params(precision=ps.FP32, max_sweeps=args.decay_sweeps, tol=1e-12,
                                              progress=10), fields=f)

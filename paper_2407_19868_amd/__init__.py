@@ -260,6 +260,18 @@ class TensorResult:
     hists: list
 
 
+def field_set(shape, dtype=torch.float64, device="cuda") -> tuple:
+    """Zeroed u, v, w, p of one grid as four views of one block, N elements apart.
+
+    The sweep reads the four fields at the same offsets: with their starts
+    N elements apart it ran fastest (256^3, FP64: 228 us per sweep; the same
+    fields shifted against each other by 32 KiB or 1-8 MiB took 235-245 us).
+    Separately allocated tensors land wherever the allocator puts them.
+    """
+    block = torch.zeros((4, *shape), dtype=dtype, device=device)
+    return tuple(block.unbind(0))
+
+
 class Context:
     """One library context on a HIP device (default: torch's current device)."""
 
@@ -368,7 +380,7 @@ class Context:
         prm = prm or params()
         dtype = torch.float32 if prm.precision == FP32 else torch.float64
         if fields is None:
-            fields = tuple(torch.zeros((nz, ny, nx), dtype=dtype, device=m.device) for _ in range(4))
+            fields = field_set((nz, ny, nx), dtype, m.device)
         f = [_dev_tensor(t, dtype, "field") for t in fields]
         h, arrs = _hist(hist_cap)
         k = np.zeros(3)
