@@ -154,6 +154,7 @@ def series_workload(args) -> dict:
             log(f"[bench] 1536^3 {form}: {gv:.1f} GVox/s ({100 * res[form]['hbm_frac']:.1f}% HBM)")
             del f
             torch.cuda.empty_cache()
+            ctx.trim()
         decay = None
         if args.decay_sweeps > 0:
             # residual history of a FP32 solve along x from rest; the tail's geometric

@@ -120,7 +120,16 @@ typedef struct {
                            axis with walls carries no through-flow: that solve is
                            PM_ERR_NO_FLOW without sweeps.  Solves only (pm_iterate
                            and pm_residual reject it).            default 0 */
-    int32_t reserved[1];
+    int32_t dc_form;    /* how PM_FP32_DC continues once the FP32 iterate s0 sits at
+                           its rounding floor: 0 correction form: s0 is kept in
+                           FP64, d0 = T(s0) - s0 is formed once by an FP64 sweep T
+                           and stored in FP32, and FP32 sweeps iterate the
+                           correction e <- A e + d0 (A: the sweep without the
+                           drive; the fixed point is s* - s0) until s0 + e meets
+                           the stop rule; if the correction reaches its own
+                           rounding floor first, or the 16 B/voxel for d0 cannot be
+                           allocated, s0 + e continues in FP64.  1: the FP32
+                           iterate is promoted and FP64 sweeps continue.  default 0 */
 } pm_params;
 
 /* Residual history: one record per check.  Host arrays of length cap owned by

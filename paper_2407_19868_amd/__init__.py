@@ -56,7 +56,7 @@ class PmParams(ctypes.Structure):
         ("progress", ctypes.c_int32),
         ("pore_cleanup", ctypes.c_int32),
         ("outer_walls", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 1),
+        ("dc_form", ctypes.c_int32),
     ]
 
 

@@ -232,6 +232,7 @@ pm_status check_params(pm_ctx *ctx, const pm_params *p)
     if (p->progress < 0) return fail(ctx, PM_ERR_ARG, "progress must be >= 0");
     if (p->pore_cleanup != 0 && p->pore_cleanup != 1) return fail(ctx, PM_ERR_ARG, "pore_cleanup must be 0 or 1");
     if (p->outer_walls < 0 || p->outer_walls > 7) return fail(ctx, PM_ERR_ARG, "outer_walls must be a bit mask 0..7");
+    if (p->dc_form != 0 && p->dc_form != 1) return fail(ctx, PM_ERR_ARG, "dc_form must be 0 or 1");
     return PM_OK;
 }
 
@@ -365,6 +366,10 @@ struct Inst {
     bool no_through_flow = false;  // outer walls close the load axis
     // state
     bool dc = false;
+    bool delta = false;      // correction form: set 0/1 hold e (FP32), user holds s0 (FP64)
+    bool to_delta = false;   // enter the correction form after this round of checks
+    void *dsrc = nullptr;    // d0 = T(s0) - s0, 4 N floats (allocated at the first use)
+    double q0[3] = {0.0, 0.0, 0.0};  // flux sums of s0
     Prec prec = kF64;
     void *set[2][4] = {};
     void *internal = nullptr;
@@ -412,9 +417,13 @@ InstDev make_dev(const Inst &in, const pm_params *prm, int64_t blk_begin, bool s
     d.nu = 1.0 / prm->re;
     d.dt = prm->dt;
     d.c2dt = prm->c2 * prm->dt;
-    d.drive = prm->drive;
+    d.drive = in.delta ? 0.0 : prm->drive;  // the correction's drive is inside d0
     d.par_off = skip ? 0 : (int)((in.local_n + 1) & 1);
     d.skip = skip ? 1 : 0;
+    for (int f = 0; f < 4; ++f)
+        d.src[f] = in.delta ? (const char *)in.dsrc + (size_t)f * in.N * sizeof(float) : nullptr;
+    d.rdt = 1.0 / prm->dt;
+    d.rc2dt = 1.0 / (prm->c2 * prm->dt);
     return d;
 }
 
@@ -614,19 +623,20 @@ struct Engine {
         h_refs.clear();
         struct Group {
             Prec prec;
+            bool src;
             int tx, ty;
             int first, count;
             int64_t blocks;
         };
         std::vector<Group> groups;
         std::vector<int> order;
-        for (int pass = 0; pass < 2; ++pass)
+        for (int pass = 0; pass < 3; ++pass)  // FP32, FP32 correction form, FP64
             for (int i : sel) {
                 const Inst &in = inst[i];
-                if ((pass == 0) != (in.prec == kF64)) continue;
-                if (groups.empty() || groups.back().prec != in.prec || groups.back().tx != in.tile.tx ||
-                    groups.back().ty != in.tile.ty)
-                    groups.push_back({in.prec, in.tile.tx, in.tile.ty, (int)h_tab.size(), 0, 0});
+                if (pass != (in.prec == kF64 ? 2 : in.delta ? 1 : 0)) continue;
+                if (groups.empty() || groups.back().prec != in.prec || groups.back().src != in.delta ||
+                    groups.back().tx != in.tile.tx || groups.back().ty != in.tile.ty)
+                    groups.push_back({in.prec, in.delta, in.tile.tx, in.tile.ty, (int)h_tab.size(), 0, 0});
                 Group &g = groups.back();
                 h_tab.push_back(dev_of(in, g.blocks, skip));
                 g.blocks += in.nblocks;
@@ -645,9 +655,14 @@ struct Engine {
         // bracket it on the caller's stream (for a graph: around the launch).
         auto enqueue = [&](hipStream_t st) -> pm_status {
             for (int j = 0; j < steps; ++j)
-                for (const Group &g : groups)
-                    PM_HIP(launch_fused(g.prec, g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1,
-                                        j == steps - 1 ? 1 : 0, st));
+                for (const Group &g : groups) {
+                    const int red = j == steps - 1 ? 1 : 0;
+                    if (g.src)
+                        PM_HIP(launch_fused_src(g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1, red, st));
+                    else
+                        PM_HIP(launch_fused(g.prec, g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1, red,
+                                            st));
+                }
             PM_HIP(launch_reduce_partials(d_refs, (int)order.size(), d_sums, st));
             PM_HIP(hipMemcpyAsync(ctx->h_sums, d_sums, order.size() * kNumSums * sizeof(double),
                                   hipMemcpyDeviceToHost, st));
@@ -656,7 +671,8 @@ struct Engine {
         if (prm->graphs && !skip) {
             std::string key = std::to_string(steps);
             for (const Group &g : groups)
-                key += "|" + std::to_string(g.prec) + ":" + std::to_string(g.tx) + "x" + std::to_string(g.ty) +
+                key += "|" + std::to_string(g.prec) + (g.src ? "s" : "") + ":" + std::to_string(g.tx) + "x" +
+                       std::to_string(g.ty) +
                        ":" + std::to_string(g.first) + ":" + std::to_string(g.count) + ":" +
                        std::to_string(g.blocks);
             key += "|" + std::to_string(order.size());
@@ -728,7 +744,9 @@ struct Engine {
         const size_t e = elem(in.prec);
         // in the final phase set 0 is the user set (FP64, FP32) -- for FP32_DC the
         // FP32 phase never finalises with status OK, but may with an error status
-        if (in.dc && in.prec == kF32) {
+        if (in.delta) {
+            PM_TRY(fold_correction(in));
+        } else if (in.dc && in.prec == kF32) {
             for (int f = 0; f < 3; ++f)
                 PM_HIP(launch_f32_to_f64((const float *)in.set[vs][f], (double *)in.user[f], in.N, stream));
             PM_HIP(launch_f32_to_f64((const float *)in.set[ps_][3], (double *)in.user[3], in.N, stream));
@@ -745,13 +763,39 @@ struct Engine {
         return PM_OK;
     }
 
-    // FP32 phase -> FP64 phase from the promoted state.
-    pm_status promote(Inst &in)
+    // s0 + e into the user fields (FP64) at the end of the correction form
+    pm_status fold_correction(Inst &in)
     {
         const int vs = (int)(in.local_n & 1), ps_ = (int)((in.local_n + 1) & 1);
         for (int f = 0; f < 3; ++f)
-            PM_HIP(launch_f32_to_f64((const float *)in.set[vs][f], (double *)in.user[f], in.N, stream));
-        PM_HIP(launch_f32_to_f64((const float *)in.set[ps_][3], (double *)in.user[3], in.N, stream));
+            PM_HIP(launch_add_f32_to_f64((const float *)in.set[vs][f], (double *)in.user[f], in.N, stream));
+        PM_HIP(launch_add_f32_to_f64((const float *)in.set[ps_][3], (double *)in.user[3], in.N, stream));
+        in.delta = false;
+        return PM_OK;
+    }
+
+    void restart_phase(Inst &in)
+    {
+        in.nblocks = blocks_of(in);
+        in.local_n = 0;
+        in.needs_start = true;
+        in.rmin = INFINITY;
+        in.stall = 0;
+        in.plateau_hits = 0;
+        in.rphase.clear();
+    }
+
+    // FP32 phase (or correction form) -> FP64 phase from the promoted state.
+    pm_status promote(Inst &in)
+    {
+        if (in.delta) {
+            PM_TRY(fold_correction(in));
+        } else {
+            const int vs = (int)(in.local_n & 1), ps_ = (int)((in.local_n + 1) & 1);
+            for (int f = 0; f < 3; ++f)
+                PM_HIP(launch_f32_to_f64((const float *)in.set[vs][f], (double *)in.user[f], in.N, stream));
+            PM_HIP(launch_f32_to_f64((const float *)in.set[ps_][3], (double *)in.user[3], in.N, stream));
+        }
         in.prec = kF64;
         for (int f = 0; f < 4; ++f) {
             in.set[0][f] = in.user[f];
@@ -767,6 +811,61 @@ struct Engine {
         in.stall = 0;
         in.plateau_hits = 0;
         in.rphase.clear();
+        return PM_OK;
+    }
+
+    // FP32 phase at its floor -> correction form (pm_params.dc_form = 0):
+    // s0 to FP64 in the user fields, one FP64 sweep T(s0) into the internal
+    // block (its sums give the flux of s0), d0 = T(s0) - s0 in FP32, and the
+    // FP32 correction e from 0 in the internal block.  Without memory for d0
+    // the state is promoted instead.
+    pm_status enter_delta(int i)
+    {
+        Inst &in = inst[i];
+        if (!in.dsrc) {
+            void *p = nullptr;
+            if (scratch.get(4 * (size_t)in.N * sizeof(float), &p) != PM_OK) {
+                ctx->err.clear();
+                return promote(in);
+            }
+            in.dsrc = p;
+        }
+        const int vs = (int)(in.local_n & 1), ps_ = (int)((in.local_n + 1) & 1);
+        for (int f = 0; f < 3; ++f)
+            PM_HIP(launch_f32_to_f64((const float *)in.set[vs][f], (double *)in.user[f], in.N, stream));
+        PM_HIP(launch_f32_to_f64((const float *)in.set[ps_][3], (double *)in.user[3], in.N, stream));
+        in.prec = kF64;
+        for (int f = 0; f < 4; ++f) {
+            in.set[0][f] = in.user[f];
+            in.set[1][f] = (char *)in.internal + (size_t)f * in.N * sizeof(double);
+        }
+        in.tile = tile_for(in, kF64);
+        in.nblocks = blocks_of(in);
+        if (in.nblocks > in.partial_rows) return fail(ctx, PM_ERR_ARG, "internal: block count grew on promotion");
+        in.local_n = 1;  // the full update, reading set 0
+        PM_TRY(run_block({i}, 1, false));
+        for (int k = 0; k < 3; ++k) in.q0[k] = sums_of[i][2 + k];
+        for (int f = 0; f < 4; ++f)
+            PM_HIP(launch_defect((const double *)in.set[1][f], (const double *)in.user[f],
+                                 (float *)in.dsrc + (size_t)f * in.N, in.N, stream));
+        in.prec = kF32;
+        in.delta = true;
+        for (int s = 0; s < 2; ++s)
+            for (int f = 0; f < 4; ++f)
+                in.set[s][f] = (char *)in.internal + (size_t)(4 * s + f) * in.N * sizeof(float);
+        PM_HIP(hipMemsetAsync(in.internal, 0, 4 * (size_t)in.N * sizeof(float), stream));
+        in.tile = tile_for(in, kF32);
+        restart_phase(in);
+        return PM_OK;
+    }
+
+    pm_status enter_pending()
+    {
+        for (int i = 0; i < (int)inst.size(); ++i)
+            if (inst[i].to_delta) {
+                inst[i].to_delta = false;
+                if (inst[i].active) PM_TRY(enter_delta(i));
+            }
         return PM_OK;
     }
 
@@ -793,8 +892,14 @@ struct Engine {
     }
 
     // Convergence bookkeeping after a check of instance `in` with sums s.
-    pm_status check(Inst &in, const double *s)
+    pm_status check(Inst &in, const double *sums)
     {
+        // in the correction form the flux sums are those of e: add those of s0
+        double s[kNumSums];
+        for (int k = 0; k < kNumSums; ++k) s[k] = sums[k];
+        const double qe = std::sqrt(s[2] * s[2] + s[3] * s[3] + s[4] * s[4]) / (double)in.N;
+        if (in.delta)
+            for (int k = 0; k < 3; ++k) s[2 + k] += in.q0[k];
         const double r = std::sqrt(s[0] + s[1]) / (prm->drive * std::sqrt((double)in.nflow));
         const double qn = std::sqrt(s[2] * s[2] + s[3] * s[3] + s[4] * s[4]) / (double)in.N;
         const double eps = (in.qprev >= 0.0 && qn > 0.0) ? std::fabs(qn - in.qprev) / qn : INFINITY;
@@ -819,13 +924,27 @@ struct Engine {
         // counts only within three decades of that level (|v| from the mean flux,
         // local velocities being larger), or after 20 checks without a new minimum:
         // a slowly decelerating residual far above the floor is not the floor.
-        const double r_floor = std::ldexp(qn, -24) / (prm->dt * prm->drive);
+        // (in the correction form: 2^-24 |e| / (dt G))
+        const double r_floor = std::ldexp(in.delta ? qe : qn, -24) / (prm->dt * prm->drive);
         const bool near_floor = r < 1e3 * r_floor;
         const bool floor = fp32_phase && ((near_floor && (in.stall >= 5 || at_fp32_floor(in))) || in.stall >= 20);
-        if (in.dc && fp32_phase) {
-            // hand over to FP64 once the FP32 iterate meets the stop rule (FP64
-            // confirms it) or sits at its rounding floor
-            if (met || floor) return promote(in);
+        if (in.dc && fp32_phase && in.delta) {
+            // correction form: s0 + e meets the stop rule, or e sits at its
+            // own rounding floor (s0 + e continues in FP64)
+            if (met) {
+                in.status = PM_OK;
+                return finalize(in);
+            }
+            if (floor) return promote(in);
+        } else if (in.dc && fp32_phase) {
+            // hand over once the FP32 iterate meets the stop rule (FP64 confirms
+            // it) or sits at its rounding floor
+            if (met) return promote(in);
+            if (floor) {
+                if (prm->dc_form == 1) return promote(in);
+                in.to_delta = true;  // after this round of checks: it launches a sweep
+                return PM_OK;
+            }
         } else if (met) {
             in.status = PM_OK;
             return finalize(in);
@@ -857,6 +976,7 @@ struct Engine {
                     inst[i].needs_start = false;
                     PM_TRY(check(inst[i], sums_of[i]));
                 }
+                PM_TRY(enter_pending());
                 continue;  // promotions inside the check restart their pipeline
             }
             int64_t remaining = INT64_MAX;
@@ -877,6 +997,7 @@ struct Engine {
                 PM_TRY(check(inst[i], sums_of[i]));
                 rworst = std::max(rworst, inst[i].r_last);
             }
+            PM_TRY(enter_pending());
             if (prm->progress > 0 && (++nchecks % prm->progress) == 0) {
                 int nact = 0;
                 for (const Inst &in : inst) nact += in.active;

@@ -22,6 +22,11 @@ struct InstDev {
     double nu, dt, c2dt, drive;
     int32_t par_off;     // effective parity = launch parity ^ par_off
     int32_t skip;        // 1: first sweep of a pipeline, pressure passes through
+    // correction form (launch_fused_src only): per-face and per-cell terms
+    // added to u, v, w and p after the update, and 1/dt, 1/(c2 dt) to fold
+    // them into the residual sums
+    const void *src[4];
+    double rdt, rc2dt;
 };
 
 // Reference to one instance's block partials for the final reduction.
@@ -54,10 +59,17 @@ hipError_t launch_mirror(const uint8_t *src, int nx, int ny, int nz, int axes, u
 // elementwise conversions and copies of n values
 hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream_t s);
+// dst += (double) src
+hipError_t launch_add_f32_to_f64(const float *src, double *dst, int64_t n, hipStream_t s);
+// d = (float)(t - s0)
+hipError_t launch_defect(const double *t, const double *s0, float *d, int64_t n, hipStream_t s);
 
 // Fused sweep over the instances of a device table (all of precision prec).
 hipError_t launch_fused(Prec prec, int tile_x, int tile_y, const InstDev *insts, int ninst,
                         int64_t nblocks, int parity, int reduce, hipStream_t s);
+// The same sweep in FP32 with the correction-form terms of InstDev::src.
+hipError_t launch_fused_src(int tile_x, int tile_y, const InstDev *insts, int ninst, int64_t nblocks, int parity,
+                            int reduce, hipStream_t s);
 bool fused_tile_supported(int tile_x, int tile_y, int prec);
 
 // Final deterministic reduction: out[i * kNumSums + j] = sum over blocks of refs[i].

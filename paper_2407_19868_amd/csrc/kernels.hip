@@ -132,6 +132,21 @@ __global__ void k_convert(const S *__restrict__ src, D *__restrict__ dst, int64_
     if (t < n) dst[t] = (D)src[t];
 }
 
+// FP32 correction added into the FP64 state
+__global__ void k_add_f32_to_f64(const float *__restrict__ src, double *__restrict__ dst, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) dst[t] += (double)src[t];
+}
+
+// increment of one FP64 sweep, t - s0, rounded to FP32
+__global__ void k_defect(const double *__restrict__ t_, const double *__restrict__ s0, float *__restrict__ d,
+                         int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) d[t] = (float)(t_[t] - s0[t]);
+}
+
 static inline unsigned grid1d(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 hipError_t launch_face_bits(const uint8_t *mask, int nx, int ny, int nz, uint32_t *bits, hipStream_t s)
@@ -275,6 +290,18 @@ hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream
     return hipGetLastError();
 }
 
+hipError_t launch_add_f32_to_f64(const float *src, double *dst, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_f32_to_f64, dim3(grid1d(n, 256)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_defect(const double *t, const double *s0, float *d, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_defect, dim3(grid1d(n, 256)), dim3(256), 0, s, t, s0, d, n);
+    return hipGetLastError();
+}
+
 // ============================================================== fused sweep
 //
 // One launch advances every instance of the table by one sweep, fusing the
@@ -347,7 +374,15 @@ struct FusedShared {
 // RED: accumulate the residual and flux sums of the state (the launches at a
 // convergence check); the other launches carry no accumulators, which keeps
 // the FP64 64x16 variant within 128 VGPRs.
-template <typename T, int TX, int TY, bool RED>
+//
+// SRC: the correction form.  The state is a correction e to a fixed state s0
+// and the sweep is e <- A e + d0, where A is the sweep without the drive and
+// d0 = T(s0) - s0 is the increment of the full sweep T at s0: the pressure
+// gradient uses p^n without d0, and d0 is added to u, v, w and p^n as they
+// are stored.  The fixed point is e* = s* - s0.  The residual of s0 + e
+// follows from linearity: F(s0 + e) = F_A(e) + d0_v / dt and
+// div(v0 + e_v) = div(e_v) - d0_p / (c2 dt); the flux sums are those of e.
+template <typename T, int TX, int TY, bool RED, bool SRC = false>
 __global__ void __launch_bounds__(TX *TY)
 k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
 {
@@ -395,6 +430,10 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
     T GLOBAL_AS *__restrict__ Wout = (T GLOBAL_AS *)I.vel[eff ^ 1][2];
     T GLOBAL_AS *__restrict__ Pout = (T GLOBAL_AS *)I.pres[eff ^ 1];
     const uint32_t GLOBAL_AS *__restrict__ codes = (const uint32_t GLOBAL_AS *)I.codes;
+    const T GLOBAL_AS *__restrict__ Su = (const T GLOBAL_AS *)I.src[0];
+    const T GLOBAL_AS *__restrict__ Sv = (const T GLOBAL_AS *)I.src[1];
+    const T GLOBAL_AS *__restrict__ Sw = (const T GLOBAL_AS *)I.src[2];
+    const T GLOBAL_AS *__restrict__ Sp = (const T GLOBAL_AS *)I.src[3];
     const T nu = (T)I.nu, dt = (T)I.dt, c2dt = (T)I.c2dt;
     const T gu = I.axis == 0 ? (T)I.drive : T(0);
     const T gv = I.axis == 1 ? (T)I.drive : T(0);
@@ -454,6 +493,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
     int z3p = wrap_int(z0 + 2, nz);   // zz + 3
     T pold = Pin[(int64_t)zcur * plane + own];
     uint32_t code = 0;
+    T sU = T(0), sV = T(0), sW = T(0), sP = T(0);  // correction-form terms of plane zz
     T hU = T(0), hV = T(0), hW = T(0), hP = T(0);
     if (has_halo) {
         hU = Uin[(int64_t)zcur * plane + hoff];
@@ -491,8 +531,16 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
         // valid); the last iteration of the chunk needs none
         const bool ahead = zz + 1 < z1;
         T bU = T(0), bV = T(0), bW = T(0), bP = T(0);
+        T bSu = T(0), bSv = T(0), bSw = T(0), bSp = T(0);
         uint32_t bC = 0;
         if (ahead) {
+            if constexpr (SRC) {
+                const int64_t oa = (int64_t)z1p * plane + own;
+                bSu = __builtin_nontemporal_load(&Su[oa]);
+                bSv = __builtin_nontemporal_load(&Sv[oa]);
+                bSw = __builtin_nontemporal_load(&Sw[oa]);
+                bSp = __builtin_nontemporal_load(&Sp[oa]);
+            }
             bU = Uin[(int64_t)z3p * plane + own];
             bV = Vin[(int64_t)z3p * plane + own];
             bW = Win[(int64_t)z2p * plane + own];
@@ -519,7 +567,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
             const T dym = divergence(su[cl - PX], su[cl - PX + 1], sv[cl - PX], Vw[2], swc[cl - PX], swn[cl - PX]);
             const T pym = skip ? sp[cl - PX] : fma(-c2dt, dym, sp[cl - PX]);
             const int64_t o = (int64_t)zcur * plane + own;
-            __builtin_nontemporal_store(pn, &Pout[o]);
+            __builtin_nontemporal_store(SRC ? pn + sP : pn, &Pout[o]);
             // u: own axis x, across y (LDS) and z (registers)
             const uint32_t cu = code;
             const T u0 = Uw[2];
@@ -528,7 +576,8 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
             const T u_d2z = d2_perp_tab(sh.tab, (cu >> 3) & 7, Uw[0], Uw[1], u0, Uw[3], Uw[4]);
             const T Fu = momentum(u_d2x, u_d2y, u_d2z, pn, pxm, nu, gu);
             const bool su_ = (cu & kSolidBit) != 0;
-            __builtin_nontemporal_store(su_ ? T(0) : fma(dt, Fu, u0), &Uout[o]);
+            __builtin_nontemporal_store(su_ ? T(0) : (SRC ? fma(dt, Fu, u0) + sU : fma(dt, Fu, u0)),
+                                        &Uout[o]);
             // v: own axis y, across x (LDS) and z (registers)
             const uint32_t cv = code >> kCodeBits;
             const T v0 = Vw[2];
@@ -537,7 +586,8 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
             const T v_d2z = d2_perp_tab(sh.tab, (cv >> 3) & 7, Vw[0], Vw[1], v0, Vw[3], Vw[4]);
             const T Fv = momentum(v_d2x, v_d2y, v_d2z, pn, pym, nu, gv);
             const bool sv_ = (cv & kSolidBit) != 0;
-            __builtin_nontemporal_store(sv_ ? T(0) : fma(dt, Fv, v0), &Vout[o]);
+            __builtin_nontemporal_store(sv_ ? T(0) : (SRC ? fma(dt, Fv, v0) + sV : fma(dt, Fv, v0)),
+                                        &Vout[o]);
             // w: own axis z (registers), across x and y (LDS)
             const uint32_t cw = code >> (2 * kCodeBits);
             const T w0 = Ww[1];
@@ -547,13 +597,24 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
             const T w_d2z = d2_own(Ww[0], w0, Ww[2]);
             const T Fw = momentum(w_d2x, w_d2y, w_d2z, pn, pn_prev, nu, gw);
             const bool sw_ = (cw & kSolidBit) != 0;
-            __builtin_nontemporal_store(sw_ ? T(0) : fma(dt, Fw, w0), &Wout[o]);
-            if (RED) {
+            __builtin_nontemporal_store(sw_ ? T(0) : (SRC ? fma(dt, Fw, w0) + sW : fma(dt, Fw, w0)),
+                                        &Wout[o]);
+            if (RED && !SRC) {
                 const double fu = su_ ? 0.0 : (double)Fu, fv = sv_ ? 0.0 : (double)Fv,
                              fw = sw_ ? 0.0 : (double)Fw;
                 acc[0] += fu * fu + fv * fv + fw * fw;
                 const double nd = (double)(nu * dvg);
                 acc[1] += nd * nd;
+            }
+            if (RED && SRC) {
+                const double fu = su_ ? 0.0 : fma((double)sU, I.rdt, (double)Fu);
+                const double fv = sv_ ? 0.0 : fma((double)sV, I.rdt, (double)Fv);
+                const double fw = sw_ ? 0.0 : fma((double)sW, I.rdt, (double)Fw);
+                acc[0] += fu * fu + fv * fv + fw * fw;
+                const double nd = (double)nu * fma(-(double)sP, I.rc2dt, (double)dvg);
+                acc[1] += nd * nd;
+            }
+            if (RED) {
                 acc[2] += (double)u0;
                 acc[3] += (double)v0;
                 acc[4] += (double)w0;
@@ -574,6 +635,10 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
         Ww[2] = bW;
         pold = bP;
         code = bC;
+        sU = bSu;
+        sV = bSv;
+        sW = bSw;
+        sP = bSp;
         hU = bhU;
         hV = bhV;
         hW = bhW;
@@ -597,7 +662,7 @@ bool fused_tile_supported(int tx, int ty, int prec)
     return (tx == 128 && ty == 8) || (tx == 64 && (ty == 8 || ty == 16)) || (tx == 32 && (ty == 8 || ty == 16));
 }
 
-template <typename T>
+template <typename T, bool SRC = false>
 static hipError_t launch_fused_t(int tx, int ty, const InstDev *insts, int ninst, int64_t nblocks, int parity,
                                  int reduce, hipStream_t s)
 {
@@ -605,11 +670,11 @@ static hipError_t launch_fused_t(int tx, int ty, const InstDev *insts, int ninst
 #define PS_FUSED_CASE(TX_, TY_)                                                                             \
     if (tx == TX_ && ty == TY_) {                                                                          \
         if (reduce)                                                                                        \
-            hipLaunchKernelGGL((k_fused<T, TX_, TY_, true>), grid, dim3(TX_ * TY_), 0, s, insts, ninst,    \
-                               parity);                                                                    \
+            hipLaunchKernelGGL((k_fused<T, TX_, TY_, true, SRC>), grid, dim3(TX_ * TY_), 0, s, insts,      \
+                               ninst, parity);                                                             \
         else                                                                                               \
-            hipLaunchKernelGGL((k_fused<T, TX_, TY_, false>), grid, dim3(TX_ * TY_), 0, s, insts, ninst,   \
-                               parity);                                                                    \
+            hipLaunchKernelGGL((k_fused<T, TX_, TY_, false, SRC>), grid, dim3(TX_ * TY_), 0, s, insts,     \
+                               ninst, parity);                                                             \
         return hipGetLastError();                                                                          \
     }
     PS_FUSED_CASE(128, 8)
@@ -628,6 +693,14 @@ hipError_t launch_fused(Prec prec, int tx, int ty, const InstDev *insts, int nin
     if (!fused_tile_supported(tx, ty, prec)) return hipErrorInvalidValue;
     return prec == kF64 ? launch_fused_t<double>(tx, ty, insts, ninst, nblocks, parity, reduce, s)
                         : launch_fused_t<float>(tx, ty, insts, ninst, nblocks, parity, reduce, s);
+}
+
+hipError_t launch_fused_src(int tx, int ty, const InstDev *insts, int ninst, int64_t nblocks, int parity,
+                            int reduce, hipStream_t s)
+{
+    if (nblocks <= 0 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (!fused_tile_supported(tx, ty, kF32)) return hipErrorInvalidValue;
+    return launch_fused_t<float, true>(tx, ty, insts, ninst, nblocks, parity, reduce, s);
 }
 
 // ============================================================== reductions

@@ -351,16 +351,68 @@ def test_solve_with_autotune_flag(ctx):
 
 
 def test_fp32_dc_hands_over_to_fp64(ctx):
-    """The FP32 phase stops at its rounding floor (or at tol) and the FP64 phase
-    restarts from the promoted state: its first record repeats the sweep count."""
+    """dc_form 1: the FP32 phase stops at its rounding floor (or at tol) and the
+    FP64 phase restarts from the promoted state: its first record repeats the
+    sweep count."""
     mask = synth.test_grid(102)
-    g = ctx.solve(ps.to_device(mask), 1, ps.params(precision=ps.FP32_DC, tol=1e-10))
+    g = ctx.solve(ps.to_device(mask), 1, ps.params(precision=ps.FP32_DC, tol=1e-10, dc_form=1))
     assert g.status == "OK"
     dup = np.nonzero(np.diff(g.hist_sweep) == 0)[0]
     assert dup.size == 1  # one hand-over: FP32 record, then FP64 record at the same sweep
     assert g.hist_r[-1] < 1e-10
+    assert ctx.last_stats()["precision"] == ps.FP64
     o = oracle.solve(mask, 1, oracle.params(tol=1e-10))
     assert normwise(g.kcol, o.kcol) <= 1e-7
+
+
+@pytest.mark.parametrize("seed", [100, 101, 102])
+def test_fp32_dc_correction_form_converges_in_fp32(ctx, seed):
+    """dc_form 0: after the FP32 phase the correction e (FP32 sweeps with the
+    FP64-formed defect of s0 as source) takes s0 + e to tol; the last sweeps
+    are FP32 and k matches the FP64 oracle at the same tol."""
+    mask = synth.test_grid(seed)
+    axis = (seed + 1) % 3
+    g = ctx.solve(ps.to_device(mask), axis, ps.params(precision=ps.FP32_DC, tol=1e-10))
+    assert g.status == "OK"
+    assert g.hist_r[-1] < 1e-10
+    dup = np.nonzero(np.diff(g.hist_sweep) == 0)[0]
+    assert dup.size == 1  # FP32 phase -> correction form, no promotion to FP64
+    assert ctx.last_stats()["precision"] == ps.FP32
+    # the record at the hand-over is the residual of s0 (from its FP64 defect):
+    # no larger than the FP32 phase's last, which carries FP32 rounding
+    assert g.hist_r[dup[0] + 1] <= 10 * g.hist_r[dup[0]]
+    o = oracle.solve(mask, axis, oracle.params(tol=1e-10))
+    assert normwise(g.kcol, o.kcol) <= 1e-7
+    f64 = ctx.solve(ps.to_device(mask), axis, ps.params(tol=1e-10))
+    for a, b in zip(g.fields, f64.fields):
+        assert a.dtype == torch.float64
+        assert float((a - b).abs().max()) <= 1e-6 * float(b.abs().max())
+
+
+def test_fp32_dc_correction_form_batch_equals_single(ctx):
+    masks = [synth.test_grid(100), synth.spheres(20, 18, 16, 2.0, 3.0, 0.5, 9)]
+    probs = [(ps.to_device(m), a) for m in masks for a in (0, 2)]
+    prm = ps.params(precision=ps.FP32_DC)
+    st, res = ctx.solve_batch(probs, prm)
+    for (m, a), r in zip(probs, res):
+        g = ctx.solve(m, a, prm)
+        assert r["status"] == g.status == "OK" and r["sweeps"] == g.sweeps
+        assert np.array_equal(r["kcol"], g.kcol)
+
+
+def test_fp32_dc_correction_form_yields_to_the_cap():
+    """Without room for the defect field the FP32 iterate is promoted instead:
+    the same result as dc_form 1."""
+    mask = synth.test_grid(100)  # 35,840 voxels: the defect field needs 573 KB
+    m = ps.to_device(mask)
+    with ps.Context(0) as c:
+        want = c.solve(m, 0, ps.params(precision=ps.FP32_DC, dc_form=1))
+        peak = c.last_stats()["peak_bytes"]
+    with ps.Context(0, mem_cap=peak + 4096) as c:
+        got = c.solve(m, 0, ps.params(precision=ps.FP32_DC))
+        assert c.last_stats()["precision"] == ps.FP64
+    assert got.status == want.status == "OK" and got.sweeps == want.sweeps
+    assert np.array_equal(got.kcol, want.kcol)
 
 
 def test_fp32_form_reaches_floor_with_k_within_1e5(ctx):
