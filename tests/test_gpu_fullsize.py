@@ -134,6 +134,21 @@ def check_sampled_one_sweep(ctx, mask, axis, prec, seed, nsamp=48, prm_kw=None):
 
 
 @pytest.mark.timeout(600)
+def test_spheres256_fp32_dc_tensor_equals_fp64(ctx, spheres256):
+    """The converged tensor of the 256^3 packing: FP32-DC (FP32 phase, then the
+    correction form) against FP64 sweeps throughout, both to r < 1e-8.  The
+    two iterates stop at different states within tol; their k agree far
+    below it."""
+    m = ps.to_device(spheres256)
+    log("[fullsize] 256^3 tensor, FP64")
+    a = ctx.tensor(m, ps.params())
+    log("[fullsize] 256^3 tensor, FP32-DC")
+    b = ctx.tensor(m, ps.params(precision=ps.FP32_DC))
+    assert a.status == b.status == "OK"
+    assert ctx.last_stats()["precision"] == ps.FP32  # the tail ran in the correction form
+    assert np.abs(b.k - a.k).max() <= 1e-9 * np.abs(a.k).max()
+
+
 def test_precipitation_batch_sampled_and_k(ctx):
     """1024x512x18 clogging series (16 states x 2 in-plane load axes = 32
     instances in one batched launch), FP32: the per-instance k after 3 sweeps
