@@ -63,8 +63,9 @@ typedef enum {
 typedef enum {
     PM_FP64 = 0,    /* FP64 fields and arithmetic                                      */
     PM_FP32 = 1,    /* FP32 fields and arithmetic, FP64 reductions                     */
-    PM_FP32_DC = 2  /* FP32 phase until the residual stalls, then FP64 defect
-                       correction from the promoted state until tol                    */
+    PM_FP32_DC = 2  /* FP32 phase until the residual stalls at its rounding floor,
+                       then an FP64 defect correction until tol (pm_params.dc_form:
+                       FP32 sweeps of the correction, or FP64 sweeps)               */
 } pm_precision;
 
 typedef enum {
