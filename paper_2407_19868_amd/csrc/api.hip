@@ -326,18 +326,13 @@ TileCfg pick_tiles(pm_ctx *ctx, const pm_params *prm, int nx, int ny, int nz, Pr
         c.zc = it->second[2];
     } else {
         // Measured on MI355X (256^3 packing, three instances per launch):
-        // FP64 64x8 (two 8-wave workgroups per CU, so one group's per-plane
-        // barrier overlaps the other's work; 128x8 reads 15 % fewer bytes but
-        // runs alone on its CU and is 1 % slower).  FP32 128x8 (2 % faster
-        // than 64x16), unless 128-wide tiles pad x more than 64-wide ones
-        // (nx = 150: 256 against 192 columns).
+        // 128x8 in both precisions (FP64 655 us against 654 for 64x16 and 672
+        // for 64x8; FP32 374 against 384 and 403), unless 128-wide tiles pad x
+        // more than 64-wide ones (nx = 150: 256 against 192 columns); then 64x16.
         const int64_t pad128 = (nx + 127) / 128 * 128, pad64 = (nx + 63) / 64 * 64;
-        c.tx = 64;
-        c.ty = 8;
-        if (prec != kF64) {
-            c.tx = pad128 <= pad64 ? 128 : 64;
-            c.ty = pad128 <= pad64 ? 8 : 16;
-        }
+        (void)prec;
+        c.tx = pad128 <= pad64 ? 128 : 64;
+        c.ty = pad128 <= pad64 ? 8 : 16;
         c.zc = 0;
     }
     if (prm->tile_x && prm->tile_y) {

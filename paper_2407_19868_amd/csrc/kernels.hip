@@ -357,6 +357,11 @@ __device__ __forceinline__ T d2_perp_tab(const CoefAB<T> *tab, uint32_t c, T vm2
     return fma(ab.a, vm1 + vp1, t);
 }
 
+template <bool B>
+struct BoolC {
+    static constexpr bool value = B;
+};
+
 // MI355X: 8 XCDs of 32 CUs; workgroup i of a dispatch goes to XCD i mod 8.
 constexpr int kNumXcd = 8;
 
@@ -507,8 +512,14 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
 
     double acc[kNumSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
-    for (int zz = z0 - 1; zz < z1; ++zz) {
-        const bool body = zz >= z0;
+    // One plane step; `body` is false for the prologue plane zz = z0 - 1, which
+    // only primes p^n and the staged planes.  The prologue is peeled off so
+    // that every step of the loop stores unconditionally: the vector-memory
+    // counter (s_waitcnt vmcnt) counts loads and stores in issue order, and a
+    // path without the stores made the compiler wait for each step's stores
+    // to complete before the loads of the next plane could be used (10 %).
+    auto plane_step = [&](const int zz, auto body_c) __attribute__((always_inline)) {
+        constexpr bool body = decltype(body_c)::value;
         T *const su = sh.u[slot];
         T *const sv = sh.v[slot];
         T *const sp = sh.p[slot];
@@ -560,7 +571,9 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
         const T dvg = divergence(Uw[2], su[cl + 1], Vw[2], sv[cl + PX], Ww[1], Ww[2]);
         const T pn = skip ? pold : fma(-c2dt, dvg, pold);
 
-        if (body && active) {
+        if constexpr (body) {
+            // lanes outside the grid hold a wrapped column: they compute and
+            // store exactly the values of that column's own lane
             // p^n of the -x and -y neighbours, from the staged planes
             const T dxm = divergence(su[cl - 1], Uw[2], sv[cl - 1], sv[cl - 1 + PX], swc[cl - 1], swn[cl - 1]);
             const T pxm = skip ? sp[cl - 1] : fma(-c2dt, dxm, sp[cl - 1]);
@@ -599,14 +612,14 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
             const bool sw_ = (cw & kSolidBit) != 0;
             __builtin_nontemporal_store(sw_ ? T(0) : (SRC ? fma(dt, Fw, w0) + sW : fma(dt, Fw, w0)),
                                         &Wout[o]);
-            if (RED && !SRC) {
+            if (RED && !SRC && active) {
                 const double fu = su_ ? 0.0 : (double)Fu, fv = sv_ ? 0.0 : (double)Fv,
                              fw = sw_ ? 0.0 : (double)Fw;
                 acc[0] += fu * fu + fv * fv + fw * fw;
                 const double nd = (double)(nu * dvg);
                 acc[1] += nd * nd;
             }
-            if (RED && SRC) {
+            if (RED && SRC && active) {
                 const double fu = su_ ? 0.0 : fma((double)sU, I.rdt, (double)Fu);
                 const double fv = sv_ ? 0.0 : fma((double)sV, I.rdt, (double)Fv);
                 const double fw = sw_ ? 0.0 : fma((double)sW, I.rdt, (double)Fw);
@@ -614,7 +627,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
                 const double nd = (double)nu * fma(-(double)sP, I.rc2dt, (double)dvg);
                 acc[1] += nd * nd;
             }
-            if (RED) {
+            if (RED && active) {
                 acc[2] += (double)u0;
                 acc[3] += (double)v0;
                 acc[4] += (double)w0;
@@ -650,7 +663,12 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
         slot ^= 1;
         wc = wn;
         wn = (wn == 2) ? 0 : wn + 1;
-    }
+    };
+    plane_step(z0 - 1, BoolC<false>{});
+    // the prologue's loads land in the registers the loop carries: complete
+    // them here, or the loop head would wait as if they were still in flight
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) expcnt(7) lgkmcnt(15)
+    for (int zz = z0; zz < z1; ++zz) plane_step(zz, BoolC<true>{});
     if (RED) block_sums(acc, sh.red, I.partials + lb * kNumSums);
 }
 
