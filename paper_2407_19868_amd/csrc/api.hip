@@ -775,6 +775,9 @@ struct Engine {
         return PM_OK;
     }
 
+    // Start a new phase (FP64 after promotion, or the correction form): a new
+    // pipeline from its own first check.  eps_q of that check must not compare
+    // with the previous phase's last check, which holds the same state.
     void restart_phase(Inst &in)
     {
         in.nblocks = blocks_of(in);
@@ -784,6 +787,7 @@ struct Engine {
         in.stall = 0;
         in.plateau_hits = 0;
         in.rphase.clear();
+        in.qprev = -1.0;
     }
 
     // FP32 phase (or correction form) -> FP64 phase from the promoted state.
@@ -806,12 +810,7 @@ struct Engine {
         const int64_t nb = blocks_of(in);
         if (nb > in.partial_rows) return fail(ctx, PM_ERR_ARG, "internal: block count grew on promotion");
         in.nblocks = nb;
-        in.local_n = 0;
-        in.needs_start = true;
-        in.rmin = INFINITY;
-        in.stall = 0;
-        in.plateau_hits = 0;
-        in.rphase.clear();
+        restart_phase(in);
         return PM_OK;
     }
 
@@ -918,7 +917,6 @@ struct Engine {
         } else {
             in.stall++;
         }
-        const bool met = prm->stop_rule == 0 ? r < prm->tol : eps < prm->tol;
         const bool fp32_phase = in.prec == kF32;
         // FP32 rounding stops the velocity updates once dt |F| falls below half an
         // ulp of the velocity: r bottoms out near 2^-24 |v| / (dt G).  A plateau
@@ -928,6 +926,9 @@ struct Engine {
         // (in the correction form: 2^-24 |e| / (dt G))
         const double r_floor = std::ldexp(in.delta ? qe : qn, -24) / (prm->dt * prm->drive);
         const bool near_floor = r < 1e3 * r_floor;
+        // Near its floor an FP32 iterate stagnates: q stops changing and eps_q
+        // reads 0 without convergence, so there eps_q does not count.
+        const bool met = prm->stop_rule == 0 ? r < prm->tol : eps < prm->tol && !(fp32_phase && near_floor);
         const bool floor = fp32_phase && ((near_floor && (in.stall >= 5 || at_fp32_floor(in))) || in.stall >= 20);
         if (in.dc && fp32_phase && in.delta) {
             // correction form: s0 + e meets the stop rule, or e sits at its

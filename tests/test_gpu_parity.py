@@ -389,6 +389,48 @@ def test_fp32_dc_correction_form_converges_in_fp32(ctx, seed):
         assert float((a - b).abs().max()) <= 1e-6 * float(b.abs().max())
 
 
+def test_fp32_dc_correction_form_eps_rule(ctx):
+    """stop_rule 1 (relative change of |q| between checks) with FP32-DC: the FP32
+    iterate's stagnation at its floor and the repeated state at a hand-over
+    (eps_q = 0 in both) do not stop the solve; it ends with the FP64 solve's k."""
+    mask = synth.test_grid(100)
+    prm = dict(stop_rule=1, tol=1e-11)
+    g = ctx.solve(ps.to_device(mask), 2, ps.params(precision=ps.FP32_DC, **prm))
+    f = ctx.solve(ps.to_device(mask), 2, ps.params(**prm))
+    assert g.status == f.status == "OK"
+    assert g.sweeps >= f.sweeps - 300
+    assert normwise(g.kcol, f.kcol) <= 1e-8
+
+
+def test_fp32_eps_rule_does_not_stop_on_stagnation(ctx):
+    """At its rounding floor an FP32 iterate stops changing and eps_q reads 0:
+    that is not convergence (the FP32 form ends NOT_CONVERGED at the floor)."""
+    mask = synth.test_grid(100)
+    g = ctx.solve(ps.to_device(mask), 2, ps.params(precision=ps.FP32, stop_rule=1, tol=1e-11))
+    assert g.status == "NOT_CONVERGED"
+    assert g.hist_r[-1] > 1e-8
+
+
+def test_fp32_dc_correction_form_stops_at_max_sweeps(ctx):
+    """A budget that ends inside the correction form returns NOT_CONVERGED with
+    s0 + e in the fields and k of the last check."""
+    mask = synth.test_grid(102)
+    m = ps.to_device(mask)
+    full = ctx.solve(m, 1, ps.params(precision=ps.FP32_DC, tol=1e-10))
+    hand = full.hist_sweep[np.nonzero(np.diff(full.hist_sweep) == 0)[0][0]]
+    assert full.sweeps > hand + 300
+    g = ctx.solve(m, 1, ps.params(precision=ps.FP32_DC, tol=1e-10, max_sweeps=int(hand) + 300))
+    assert g.status == "NOT_CONVERGED" and g.sweeps == hand + 300
+    assert ctx.last_stats()["precision"] == ps.FP32
+    # identical history up to the budget: the same sweeps in the same order
+    n = len(g.hist_r)
+    assert np.array_equal(g.hist_r, full.hist_r[:n])
+    assert normwise(g.kcol, full.hist_q[n - 1] / 0.01) <= 1e-12  # k = q / (Re G)
+    assert normwise(g.kcol, full.kcol) <= 1e-4
+    for t in g.fields:
+        assert bool(torch.isfinite(t).all())
+
+
 def test_fp32_dc_correction_form_batch_equals_single(ctx):
     masks = [synth.test_grid(100), synth.spheres(20, 18, 16, 2.0, 3.0, 0.5, 9)]
     probs = [(ps.to_device(m), a) for m in masks for a in (0, 2)]
