@@ -85,7 +85,7 @@ def test_converged_k_equals_direct_solve(mi):
     mask = small_masks()[mi]
     prm = oracle.params(tol=1e-12)
     sols = [direct.solve_steady(mask, axis) for axis in range(3)]
-    # normwise: a blocked direction has k ~ 0, judged against the largest entry
+    # normwise: a blocked direction has k ~ 0, measured against the largest entry
     kscale = max(np.abs(s[0]).max() for s in sols)
     for axis in range(3):
         kd, ud, vd, wd, pd, lam = sols[axis]
