@@ -135,6 +135,23 @@ def test_kernel_variants_bitwise(ctx, name, prec):
             assert np.array_equal(g, r), (tx, ty, zc)
 
 
+@pytest.mark.parametrize("shape", [(512, 128, 6), (520, 130, 5)])
+@pytest.mark.parametrize("prec", [ps.FP64, ps.FP32])
+def test_rotated_block_order_bitwise(ctx, shape, prec):
+    """Planes of at least 256 tiles (32x8 tiles here: 256 and 289 per plane,
+    the second with ragged edges and an uneven split over the XCDs) take the
+    rotated block order; the iterates stay bitwise equal to the two-pass
+    kernel's, and to a decomposition without rotation (64 tiles per plane)."""
+    nx, ny, nz = shape
+    mask = synth.spheres(nx, ny, nz, 2.0, 4.0, 0.5, 31)
+    st = random_state(mask, 6)
+    ref = gpu_iterate(ctx, mask, 0, st, 5, prec, kernel=ps.KERNEL_SIMPLE)
+    for tx, ty, zc in [(32, 8, 2), (32, 8, 0), (64, 16, 0)]:
+        got = gpu_iterate(ctx, mask, 0, st, 5, prec, kernel=ps.KERNEL_FUSED, tile_x=tx, tile_y=ty, zchunk=zc)
+        for g, r in zip(got, ref):
+            assert np.array_equal(g, r), (tx, ty, zc)
+
+
 def test_iterate_fp32_against_oracle(ctx):
     mask = MASKS["spheres_70x13x11"]()
     st = random_state(mask, 3)
