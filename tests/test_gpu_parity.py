@@ -152,6 +152,27 @@ def test_rotated_block_order_bitwise(ctx, shape, prec):
             assert np.array_equal(g, r), (tx, ty, zc)
 
 
+@pytest.mark.parametrize("shape", [(512, 128, 6), (520, 130, 5)])
+def test_round_major_order_bitwise(ctx, shape):
+    """FP64 workgroups of 1024 threads take the round-major order: one-plane
+    z-chunks give 384 and 425 workgroups (a full round of 256 and a partial
+    one, split unevenly over the XCDs).  Iterates and residual sums stay
+    bitwise equal to the two-pass kernel's."""
+    nx, ny, nz = shape
+    mask = synth.spheres(nx, ny, nz, 2.0, 4.0, 0.5, 32)
+    st = random_state(mask, 7)
+    ref = gpu_iterate(ctx, mask, 1, st, 5, kernel=ps.KERNEL_SIMPLE)
+    for tx, ty, zc in [(64, 16, 1), (128, 8, 1), (128, 8, 0)]:
+        got = gpu_iterate(ctx, mask, 1, st, 5, kernel=ps.KERNEL_FUSED, tile_x=tx, tile_y=ty, zchunk=zc)
+        for g, r in zip(got, ref):
+            assert np.array_equal(g, r), (tx, ty, zc)
+    m = ps.to_device(mask)
+    a = ctx.solve(m, 1, ps.params(max_sweeps=300, tile_x=128, tile_y=8, zchunk=1))
+    b = ctx.solve(m, 1, ps.params(max_sweeps=300, tile_x=64, tile_y=8, zchunk=1))
+    assert a.sweeps == b.sweeps == 300
+    assert normwise(a.kcol, b.kcol) <= 1e-13
+
+
 def test_iterate_fp32_against_oracle(ctx):
     mask = MASKS["spheres_70x13x11"]()
     st = random_state(mask, 3)
