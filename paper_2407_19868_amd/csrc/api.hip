@@ -396,6 +396,12 @@ int64_t blocks_of(const Inst &in)
 size_t elem(Prec p) { return p == kF64 ? sizeof(double) : sizeof(float); }
 
 // Device-table entry of an instance (sweep n reads set n & 1 when par_off = 0 and parity = n & 1).
+bool alone_of(const Inst &in)
+{
+    const int64_t tiles = (int64_t)((in.nx + in.tile.tx - 1) / in.tile.tx) * ((in.ny + in.tile.ty - 1) / in.tile.ty);
+    return fused_alone(in.prec, in.tile.tx, in.tile.ty, tiles);
+}
+
 InstDev make_dev(const Inst &in, const pm_params *prm, int64_t blk_begin, bool skip)
 {
     InstDev d;
@@ -624,7 +630,7 @@ struct Engine {
         h_refs.clear();
         struct Group {
             Prec prec;
-            bool src;
+            bool src, alone;
             int tx, ty;
             int first, count;
             int64_t blocks;
@@ -635,9 +641,10 @@ struct Engine {
             for (int i : sel) {
                 const Inst &in = inst[i];
                 if (pass != (in.prec == kF64 ? 2 : in.delta ? 1 : 0)) continue;
+                const bool alone = alone_of(in);
                 if (groups.empty() || groups.back().prec != in.prec || groups.back().src != in.delta ||
-                    groups.back().tx != in.tile.tx || groups.back().ty != in.tile.ty)
-                    groups.push_back({in.prec, in.delta, in.tile.tx, in.tile.ty, (int)h_tab.size(), 0, 0});
+                    groups.back().alone != alone || groups.back().tx != in.tile.tx || groups.back().ty != in.tile.ty)
+                    groups.push_back({in.prec, in.delta, alone, in.tile.tx, in.tile.ty, (int)h_tab.size(), 0, 0});
                 Group &g = groups.back();
                 h_tab.push_back(dev_of(in, g.blocks, skip));
                 g.blocks += in.nblocks;
@@ -659,10 +666,11 @@ struct Engine {
                 for (const Group &g : groups) {
                     const int red = j == steps - 1 ? 1 : 0;
                     if (g.src)
-                        PM_HIP(launch_fused_src(g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1, red, st));
+                        PM_HIP(launch_fused_src(g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1, red, st,
+                                                g.alone));
                     else
                         PM_HIP(launch_fused(g.prec, g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1, red,
-                                            st));
+                                            st, g.alone));
                 }
             PM_HIP(launch_reduce_partials(d_refs, (int)order.size(), d_sums, st));
             PM_HIP(hipMemcpyAsync(ctx->h_sums, d_sums, order.size() * kNumSums * sizeof(double),
@@ -672,7 +680,8 @@ struct Engine {
         if (prm->graphs && !skip) {
             std::string key = std::to_string(steps);
             for (const Group &g : groups)
-                key += "|" + std::to_string(g.prec) + (g.src ? "s" : "") + ":" + std::to_string(g.tx) + "x" +
+                key += "|" + std::to_string(g.prec) + (g.src ? "s" : "") + (g.alone ? "a" : "") + ":" +
+                       std::to_string(g.tx) + "x" +
                        std::to_string(g.ty) +
                        ":" + std::to_string(g.first) + ":" + std::to_string(g.count) + ":" +
                        std::to_string(g.blocks);
@@ -1079,11 +1088,12 @@ pm_status autotune_shape(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx
         d[1].par_off = 1;
         PM_HIP(hipMemcpyAsync(tab, d, sizeof d, hipMemcpyHostToDevice, s));
         InstDev *dt = (InstDev *)tab;
-        PM_HIP(launch_fused(prec, c.tx, c.ty, dt, 1, in.nblocks, 0, 0, s));
-        PM_HIP(launch_fused(prec, c.tx, c.ty, dt + 1, 1, in.nblocks, 0, 0, s));
+        const bool alone = alone_of(in);
+        PM_HIP(launch_fused(prec, c.tx, c.ty, dt, 1, in.nblocks, 0, 0, s, alone));
+        PM_HIP(launch_fused(prec, c.tx, c.ty, dt + 1, 1, in.nblocks, 0, 0, s, alone));
         PM_HIP(hipEventRecord(ctx->ev[0], s));
         for (int r = 0; r < reps; ++r)
-            PM_HIP(launch_fused(prec, c.tx, c.ty, dt + 1, 1, in.nblocks, (r + 1) & 1, 0, s));
+            PM_HIP(launch_fused(prec, c.tx, c.ty, dt + 1, 1, in.nblocks, (r + 1) & 1, 0, s, alone));
         PM_HIP(hipEventRecord(ctx->ev[1], s));
         PM_HIP(hipEventSynchronize(ctx->ev[1]));
         float ms = 0.f;
@@ -1509,9 +1519,10 @@ pm_status pm_iterate(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx,
     PM_HIP(hipMemcpyAsync(tab, d, sizeof d, hipMemcpyHostToDevice, s));
     InstDev *dt = (InstDev *)tab;
     PM_TRY(stats_mark(ctx, s, true));
-    PM_HIP(launch_fused(prec, in.tile.tx, in.tile.ty, dt, 1, in.nblocks, 0, 0, s));
+    const bool alone = alone_of(in);
+    PM_HIP(launch_fused(prec, in.tile.tx, in.tile.ty, dt, 1, in.nblocks, 0, 0, s, alone));
     for (int64_t n = 1; n <= count; ++n)
-        PM_HIP(launch_fused(prec, in.tile.tx, in.tile.ty, dt + 1, 1, in.nblocks, (int)((n - 1) & 1), 0, s));
+        PM_HIP(launch_fused(prec, in.tile.tx, in.tile.ty, dt + 1, 1, in.nblocks, (int)((n - 1) & 1), 0, s, alone));
     PM_TRY(stats_mark(ctx, s, false, count + 1, (count + 1) * N));
     ctx->stats.tile_x = in.tile.tx;
     ctx->stats.tile_y = in.tile.ty;

@@ -65,11 +65,18 @@ hipError_t launch_add_f32_to_f64(const float *src, double *dst, int64_t n, hipSt
 hipError_t launch_defect(const double *t, const double *s0, float *d, int64_t n, hipStream_t s);
 
 // Fused sweep over the instances of a device table (all of precision prec).
+// alone: reserve LDS so that each CU holds one workgroup (see fused_alone).
 hipError_t launch_fused(Prec prec, int tile_x, int tile_y, const InstDev *insts, int ninst,
-                        int64_t nblocks, int parity, int reduce, hipStream_t s);
+                        int64_t nblocks, int parity, int reduce, hipStream_t s,
+                        bool alone = false);
 // The same sweep in FP32 with the correction-form terms of InstDev::src.
 hipError_t launch_fused_src(int tile_x, int tile_y, const InstDev *insts, int ninst, int64_t nblocks, int parity,
-                            int reduce, hipStream_t s);
+                            int reduce, hipStream_t s, bool alone = false);
+// Whether a sweep of this precision and tile over planes of tiles_per_plane
+// tiles runs one workgroup per CU: FP32 1024-thread tiles on planes of at least
+// 1024 tiles measured 5-8 % faster so (1024^3, 1536^3) and 0 to -3.5 % on
+// smaller planes (256^3 to 768^3, 1024 x 512 slabs).
+bool fused_alone(Prec prec, int tx, int ty, int64_t tiles_per_plane);
 bool fused_tile_supported(int tile_x, int tile_y, int prec);
 
 // Final deterministic reduction: out[i * kNumSums + j] = sum over blocks of refs[i].

@@ -704,6 +704,11 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
     if (RED) block_sums(acc, sh.red, I.partials + lb * kNumSums);
 }
 
+bool fused_alone(Prec prec, int tx, int ty, int64_t tiles_per_plane)
+{
+    return prec == kF32 && tx * ty == 1024 && tiles_per_plane >= 1024;
+}
+
 bool fused_tile_supported(int tx, int ty, int prec)
 {
     // one halo position per thread; LDS rings within a workgroup's 160 KiB
@@ -712,18 +717,28 @@ bool fused_tile_supported(int tx, int ty, int prec)
     return (tx == 128 && ty == 8) || (tx == 64 && (ty == 8 || ty == 16)) || (tx == 32 && (ty == 8 || ty == 16));
 }
 
+// Dynamic LDS (the kernel does not touch it) that takes a workgroup's share
+// of the CU's 160 KiB past one half: one workgroup per CU.
+template <typename T, int TX, int TY>
+static unsigned one_per_cu_lds()
+{
+    constexpr size_t half = 80 * 1024, st = sizeof(FusedShared<T, TX, TY>);
+    return st > half ? 0u : (unsigned)(half - st + 256);
+}
+
 template <typename T, bool SRC = false>
 static hipError_t launch_fused_t(int tx, int ty, const InstDev *insts, int ninst, int64_t nblocks, int parity,
-                                 int reduce, hipStream_t s)
+                                 int reduce, hipStream_t s, bool alone)
 {
     const dim3 grid((unsigned)nblocks);
 #define PS_FUSED_CASE(TX_, TY_)                                                                             \
     if (tx == TX_ && ty == TY_) {                                                                          \
+        const unsigned dyn = alone ? one_per_cu_lds<T, TX_, TY_>() : 0u;                                   \
         if (reduce)                                                                                        \
-            hipLaunchKernelGGL((k_fused<T, TX_, TY_, true, SRC>), grid, dim3(TX_ * TY_), 0, s, insts,      \
+            hipLaunchKernelGGL((k_fused<T, TX_, TY_, true, SRC>), grid, dim3(TX_ * TY_), dyn, s, insts,    \
                                ninst, parity);                                                             \
         else                                                                                               \
-            hipLaunchKernelGGL((k_fused<T, TX_, TY_, false, SRC>), grid, dim3(TX_ * TY_), 0, s, insts,     \
+            hipLaunchKernelGGL((k_fused<T, TX_, TY_, false, SRC>), grid, dim3(TX_ * TY_), dyn, s, insts,   \
                                ninst, parity);                                                             \
         return hipGetLastError();                                                                          \
     }
@@ -737,20 +752,20 @@ static hipError_t launch_fused_t(int tx, int ty, const InstDev *insts, int ninst
 }
 
 hipError_t launch_fused(Prec prec, int tx, int ty, const InstDev *insts, int ninst, int64_t nblocks, int parity,
-                        int reduce, hipStream_t s)
+                        int reduce, hipStream_t s, bool alone)
 {
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
     if (!fused_tile_supported(tx, ty, prec)) return hipErrorInvalidValue;
-    return prec == kF64 ? launch_fused_t<double>(tx, ty, insts, ninst, nblocks, parity, reduce, s)
-                        : launch_fused_t<float>(tx, ty, insts, ninst, nblocks, parity, reduce, s);
+    return prec == kF64 ? launch_fused_t<double>(tx, ty, insts, ninst, nblocks, parity, reduce, s, alone)
+                        : launch_fused_t<float>(tx, ty, insts, ninst, nblocks, parity, reduce, s, alone);
 }
 
 hipError_t launch_fused_src(int tx, int ty, const InstDev *insts, int ninst, int64_t nblocks, int parity,
-                            int reduce, hipStream_t s)
+                            int reduce, hipStream_t s, bool alone)
 {
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
     if (!fused_tile_supported(tx, ty, kF32)) return hipErrorInvalidValue;
-    return launch_fused_t<float, true>(tx, ty, insts, ninst, nblocks, parity, reduce, s);
+    return launch_fused_t<float, true>(tx, ty, insts, ninst, nblocks, parity, reduce, s, alone);
 }
 
 // ============================================================== reductions
