@@ -308,8 +308,9 @@ int auto_zc(int nx, int ny, int nz, int tx, int ty)
     const int64_t txy = (int64_t)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
     // aim for 512 * 512 threads in flight (512 workgroups of 512 threads, 256 of
     // 1024: at least one 16-wave group per CU) while keeping chunks long enough
-    // to amortise priming the z window (the prologue reads 4 extra planes of u
-    // and v, 2 of w); chunks of up to 64 planes measured best (16 to 256 tried)
+    // to amortise priming the z window (each chunk also reads the planes just
+    // below and above it); chunks of up to 64 planes measured best (16 to 256
+    // tried)
     int64_t zc = (int64_t)nz * txy * tx * ty / (512LL * 512LL);
     // small grids cannot fill the chip even with 16-plane chunks: there the sweep
     // is latency-bound (one plane after another per workgroup), so shorter chunks
