@@ -297,7 +297,7 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py measures one GPU: this build runs the solver on a single MI355X "
+        print(f"bench.py measures one GPU: the solver runs on a single MI355X "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}); multi-GPU sharding is a "
               f"design note only.", file=sys.stderr)
         return 2
