@@ -173,6 +173,19 @@ def test_round_major_order_bitwise(ctx, shape):
     assert normwise(a.kcol, b.kcol) <= 1e-13
 
 
+def test_one_workgroup_per_cu_bitwise(ctx):
+    """FP32 1024-thread tiles on planes of 1024 tiles (1024 x 1024) launch with
+    the LDS reservation that leaves one workgroup per CU; the iterates stay
+    bitwise equal to the two-pass kernel's."""
+    mask = synth.spheres(1024, 1024, 3, 3.0, 6.0, 0.5, 33)
+    st = random_state(mask, 8)
+    ref = gpu_iterate(ctx, mask, 2, st, 3, ps.FP32, kernel=ps.KERNEL_SIMPLE)
+    for tx, ty in [(128, 8), (64, 16)]:
+        got = gpu_iterate(ctx, mask, 2, st, 3, ps.FP32, kernel=ps.KERNEL_FUSED, tile_x=tx, tile_y=ty)
+        for g, r in zip(got, ref):
+            assert np.array_equal(g, r), (tx, ty)
+
+
 def test_iterate_fp32_against_oracle(ctx):
     mask = MASKS["spheres_70x13x11"]()
     st = random_state(mask, 3)
