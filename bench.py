@@ -89,22 +89,71 @@ def calibrate_copy() -> int:
     return 0
 
 
-def cpu_baseline(mask, seconds: float):
-    """Oracle sweeps of one load axis from rest, count calibrated to ~`seconds`."""
+def cpu_model() -> str:
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def oracle_rate(mask, seconds: float, threads: int):
+    """Oracle sweeps of one load axis from rest on `threads` threads, the count
+    calibrated to ~`seconds`; returns (GVoxel-updates/s, sweeps, seconds)."""
     import oracle
     nz, ny, nx = mask.shape
+    oracle.set_threads(threads)
     oracle.run_sweeps(mask, 0, 1)  # first touch of the buffers
     t0 = time.perf_counter()
-    oracle.run_sweeps(mask, 0, 3)
-    t3 = (time.perf_counter() - t0) / 3.0
-    n = max(1, int(round(seconds / max(t3, 1e-6))))
+    oracle.run_sweeps(mask, 0, 2)
+    t2 = (time.perf_counter() - t0) / 2.0
+    n = max(1, int(round(seconds / max(t2, 1e-6))))
     t0 = time.perf_counter()
     oracle.run_sweeps(mask, 0, n)
     dt = time.perf_counter() - t0
-    return {"value": nx * ny * nz * n / dt / 1e9, "unit": "GVoxel-updates/s",
-            "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"{n} FP64 sweeps of load axis x of the {nx}x{ny}x{nz} packing from rest "
-                      f"({dt:.1f} s)"}
+    return nx * ny * nz * n / dt / 1e9, n, dt
+
+
+def cpu_baseline(mask, seconds: float):
+    """The oracle (plain C, FP64, OpenMP loops) on one thread and on every
+    thread the process may use, each on a bounded sample of the workload."""
+    import oracle
+    nz, ny, nx = mask.shape
+    all_threads = oracle.max_threads()
+    v1, n1, d1 = oracle_rate(mask, seconds / 2, 1)
+    va, na, da = oracle_rate(mask, seconds, all_threads)
+    oracle.set_threads(all_threads)
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"value": va, "unit": "GVoxel-updates/s", "cores": all_threads, "kind": "oracle",
+            "sample": f"{na} FP64 sweeps of load axis x of the {nx}x{ny}x{nz} packing from rest on "
+                      f"{all_threads} threads ({da:.1f} s); {n1} sweeps on 1 thread ({d1:.1f} s)",
+            "threads_1": {"value": v1, "sweeps": n1, "seconds": round(d1, 2)},
+            "threads_all": {"value": va, "threads": all_threads, "sweeps": na, "seconds": round(da, 2)},
+            "cpu_model": cpu_model(), "nproc": nproc,
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+
+
+def k_error_table(k, ref) -> dict:
+    """Entry-wise error of a 3x3 tensor against a reference: |dk_ij| / |ref_ij|
+    (relative) and |dk_ij| / max |ref| (normwise, meaningful for the small
+    off-diagonals)."""
+    import numpy as np
+    k, ref = np.asarray(k, dtype=float), np.asarray(ref, dtype=float)
+    d = np.abs(k - ref)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rel = np.where(ref != 0, d / np.abs(ref), np.where(d == 0, 0.0, np.inf))
+    nw = d / np.abs(ref).max()
+    return {"relative": [[float(f"{x:.3g}") for x in row] for row in rel],
+            "normwise": [[float(f"{x:.3g}") for x in row] for row in nw],
+            "max_normwise": float(f"{nw.max():.3g}")}
 
 
 def tile_override(args) -> dict:
@@ -415,6 +464,7 @@ def main() -> int:
             log(f"[bench] time-to-tensor {name}: {dt:.2f} s, sweeps {list(r.sweeps)}, status {r.status}")
         err = float(np.abs(ks["fp32_dc"] - ks["fp64"]).max() / np.abs(ks["fp64"]).max())
         tt["fp32_dc_vs_fp64_k_rel"] = err
+        tt["fp32_dc_vs_fp64_k_err_table"] = k_error_table(ks["fp32_dc"], ks["fp64"])
         tt["speedup_fp32_dc"] = round(tt["fp64"]["seconds"] / tt["fp32_dc"]["seconds"], 3)
         pa = ps.principal_axes(ks["fp64"], 0.05)
         tt["principal_fp64"] = {"k_I_II_III": [float(f"{x:.8g}") for x in pa.lam], "class": pa.cls,
@@ -438,6 +488,24 @@ def main() -> int:
         log(f"[bench] 32^3 single solve: {dt1 * 1e3:.1f} ms, {r1.sweeps} sweeps")
 
     if not args.no_cpu:
+        # every k_ij of the GPU tensors against the FP64 oracle's, on a packing the
+        # oracle converges in seconds
+        import oracle
+        log("[bench] 48^3 tensor: GPU FP64 and FP32-DC against the oracle")
+        m48_np = synth.spheres(48, 48, 48, 3.0, 5.0, 0.35, 6)
+        m48 = ps.to_device(m48_np)
+        t0 = time.perf_counter()
+        ko, _, ro = oracle.tensor(m48_np, oracle.params())
+        t_or = time.perf_counter() - t0
+        kerr = {"workload": "overlapping spheres 48^3, radius U[3,5], porosity 0.35, seed 6; tol 1e-8",
+                "oracle_seconds": round(t_or, 2), "oracle_status": [r.status for r in ro],
+                "oracle_sweeps": [int(r.sweeps) for r in ro]}
+        for name, pr in (("fp64", ps.FP64), ("fp32_dc", ps.FP32_DC)):
+            g = ctx.tensor(m48, ps.params(precision=pr))
+            kerr[name] = {"status": g.status, "sweeps": [int(x) for x in g.sweeps],
+                          "vs_oracle": k_error_table(g.k, ko)}
+        log(f"[bench] 48^3 k error vs oracle: FP64 {kerr['fp64']['vs_oracle']['max_normwise']:.2e}, "
+            f"FP32-DC {kerr['fp32_dc']['vs_oracle']['max_normwise']:.2e}")
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(mask_np, args.cpu_seconds)
         if "single_solve_32" in out:
@@ -449,6 +517,7 @@ def main() -> int:
                 "seconds": round(dto, 3), "status": o1.status, "sweeps": int(o1.sweeps),
                 "k_rel_diff_gpu": float(np.abs(np.asarray(o1.kcol) - r1.kcol).max() / np.abs(o1.kcol).max())}
             log(f"[bench] oracle 32^3 single solve: {dto:.2f} s")
+        out["cpu_baseline"]["k_error_48"] = kerr
         log(f"[bench] oracle {out['cpu_baseline']['value']:.4f} GVox/s on "
             f"{out['cpu_baseline']['cores']} threads")
     ctx.close()

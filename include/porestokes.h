@@ -94,8 +94,9 @@ typedef struct {
     int32_t tile_y;     /* one of 128x8, 64x8, 64x16, 32x8, 32x16                   */
     int32_t zchunk;     /* planes per workgroup along z (0 = auto)                   */
     int32_t graphs;     /* 1: each block of check_every sweeps (plus its reduction
-                           and copy-back) is captured once as a HIP graph and
-                           replayed; 0: launched directly.      default 1            */
+                           and copy-back) is captured once as HIP graphs (the
+                           two-sweep launches, then the rest) and replayed; 0:
+                           launched directly.                    default 1            */
     int32_t autotune;   /* 1: before solving, time the fused-kernel decompositions
                            on each new (shape, precision) and keep the fastest in
                            the context (see pm_autotune).        default 0            */
@@ -131,6 +132,16 @@ typedef struct {
                            rounding floor first, or the 16 B/voxel for d0 cannot be
                            allocated, s0 + e continues in FP64.  1: the FP32
                            iterate is promoted and FP64 sweeps continue.  default 0 */
+    int32_t tblock;     /* sweeps per HBM pass of the fused kernel: 1, or 2 (temporal
+                           blocking: two sweeps per read and write of the fields;
+                           the first sweep of a solve, the sweep of each residual
+                           check and the correction form run as single sweeps); 0:
+                           the autotuned choice for the shape, else 1.  Results are
+                           bitwise the same for every value.     default 0            */
+    int32_t tile2_x;    /* two-sweep kernel output tile override (0 = auto);         */
+    int32_t tile2_y;    /* (tile2_x, tile2_y) one of 64x10, 64x8, 64x6, 32x24, 32x12,
+                           32x8                                                      */
+    int32_t zchunk2;    /* planes per two-sweep workgroup along z (0 = auto)         */
 } pm_params;
 
 /* Residual history: one record per check.  Host arrays of length cap owned by
@@ -237,7 +248,10 @@ pm_status pm_solve(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, i
 
 /*
  * Full tensor (§2 eq. 3dK; App. C): the three load cases x, y, z solved as one
- * batch.  k (host, 9 doubles, row-major k[i*3+j] = k_ij, column j from load
+ * batch when their device buffers fit beside each other (within the context
+ * cap and the device's free memory), else one after another; each load case
+ * gives the same result either way (pm_stats.tensor_cases_at_once tells which
+ * ran).  k (host, 9 doubles, row-major k[i*3+j] = k_ij, column j from load
  * axis j) and k_sym = (k + k^T)/2 (host, 9).  hist: host array of 3 histories
  * or NULL.  sweeps: host array of 3 or NULL.  Fields are kept internally.
  */
@@ -271,17 +285,21 @@ pm_status pm_solve_batch(pm_ctx *ctx, void *stream, pm_instance *inst, int32_t n
                          const pm_params *params);
 
 /*
- * Autotuner: time the fused sweep for each supported decomposition (tile
- * 64x8, 32x8, 32x16 and 64x16; z-chunks 16..128 planes) on this mask
- * and precision (PM_FP64 or PM_FP32), from rest, and keep the fastest for the
- * shape (nx, ny, nz) in the context; later solves of that shape use it unless
- * params fix a tile.  If the environment variable PORESTOKES_TUNE_CACHE names
- * a file, choices are loaded from it at pm_create and written back here (a
- * flat JSON object "NXxNYxNZ:f64" -> [tile_x, tile_y, zchunk]).  best (host,
- * 3 ints, may be NULL) receives the choice.  Synchronises the stream.
+ * Autotuner: time the fused sweep for each supported decomposition on this
+ * mask and precision (PM_FP64 or PM_FP32), from rest: the single-step tiles
+ * (128x8, 64x8, 32x8, 32x16, 64x16) with z-chunks of 16..128 planes, and the
+ * two-step kernel (two sweeps per pass, pm_params.tblock) with output tiles
+ * 64x10, 64x8, 64x6, 32x24, 32x12, 32x8 and its z-chunks, each priced per sweep.  The
+ * fastest choice is kept for the shape (nx, ny, nz) in the context; later
+ * solves of that shape use it unless params fix a tile or tblock.  If the
+ * environment variable PORESTOKES_TUNE_CACHE names a file, choices are loaded
+ * from it at pm_create and written back here (a flat JSON object
+ * "NXxNYxNZ:f64" -> [tile_x, tile_y, zchunk, tblock, tile2_x, tile2_y, zchunk2]).
+ * best (host, 7 ints, may be NULL) receives the choice in that order.
+ * Synchronises the stream.
  */
 pm_status pm_autotune(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny,
-                      int64_t nz, int precision, int32_t best[3]);
+                      int64_t nz, int precision, int32_t best[7]);
 
 /* Timing of the sweep kernels of the last pm_iterate / pm_solve / pm_tensor /
  * pm_solve_batch call on a context, measured with HIP events recorded on the
@@ -298,6 +316,19 @@ typedef struct {
     int64_t peak_bytes;      /* most device memory the call had in use at once (the
                                 library's own allocations, not the caller's buffers,
                                 not blocks kept idle for later calls)                    */
+    int32_t tblock;          /* sweeps per pass of the last sweep launch (pm_params.tblock) */
+    int32_t tensor_cases_at_once; /* pm_tensor: 3 when the three load cases ran as one
+                                batch, 1 when they did not fit beside each other and
+                                ran one after another (then the counts and times are
+                                summed over the three calls); 0 for other calls         */
+    int32_t dc_promoted_for_memory; /* PM_FP32_DC instances whose correction form could
+                                not allocate its defect field and continued as FP64
+                                sweeps instead (dc_form 1 behaviour)                     */
+    int32_t reserved;
+    int64_t t2_launches;     /* two-step launches among sweep_launches (tblock 2)         */
+    int64_t t2_voxels;       /* voxels those launches passed over (each advanced 2 sweeps) */
+    double t2_ms;            /* GPU time spanned by the runs of consecutive two-step launches
+                                (HIP events on the call's stream)                         */
 } pm_stats;
 
 /* Copy the statistics of the last call into *out (host). */

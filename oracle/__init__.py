@@ -99,6 +99,8 @@ def _load():
     lib.orc_run_sweeps.restype = i32
     lib.orc_max_threads.argtypes = []
     lib.orc_max_threads.restype = i32
+    lib.orc_set_threads.argtypes = [i32]
+    lib.orc_set_threads.restype = None
     _lib = lib
     return lib
 
@@ -116,6 +118,11 @@ def _mask(mask) -> np.ndarray:
 
 def max_threads() -> int:
     return int(_load().orc_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (n >= 1)."""
+    _load().orc_set_threads(int(n))
 
 
 # ------------------------------------------------------------------ flags

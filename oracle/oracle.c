@@ -450,6 +450,17 @@ int orc_run_sweeps(const orc_params *prm, const uint8_t *mask, int64_t nx, int64
     return ORC_OK;
 }
 
+/* Threads of the OpenMP loops (the CPU baseline times one thread and all). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_max_threads(void)
 {
 #ifdef _OPENMP

@@ -57,6 +57,10 @@ class PmParams(ctypes.Structure):
         ("pore_cleanup", ctypes.c_int32),
         ("outer_walls", ctypes.c_int32),
         ("dc_form", ctypes.c_int32),
+        ("tblock", ctypes.c_int32),
+        ("tile2_x", ctypes.c_int32),
+        ("tile2_y", ctypes.c_int32),
+        ("zchunk2", ctypes.c_int32),
     ]
 
 
@@ -104,6 +108,13 @@ class PmStats(ctypes.Structure):
         ("zchunk", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("peak_bytes", ctypes.c_int64),
+        ("tblock", ctypes.c_int32),
+        ("tensor_cases_at_once", ctypes.c_int32),
+        ("dc_promoted_for_memory", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("t2_launches", ctypes.c_int64),
+        ("t2_voxels", ctypes.c_int64),
+        ("t2_ms", ctypes.c_double),
     ]
 
 
@@ -319,9 +330,10 @@ class Context:
         self._check(self._lib.pm_trim(self._h))
 
     def autotune(self, mask, precision: int = FP64) -> tuple:
-        """Time the fused-kernel decompositions on this mask; returns (tile_x, tile_y, zchunk)."""
+        """Time the fused-kernel decompositions on this mask; returns (tile_x, tile_y, zchunk,
+        tblock, tile2_x, tile2_y, zchunk2)."""
         m, nx, ny, nz = _mask3(mask)
-        best = np.zeros(3, dtype=np.int32)
+        best = np.zeros(7, dtype=np.int32)
         self._check(self._lib.pm_autotune(self._h, _stream(), m.data_ptr(), nx, ny, nz, precision,
                                           best.ctypes.data))
         return tuple(int(v) for v in best)

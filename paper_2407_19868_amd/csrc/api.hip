@@ -33,7 +33,7 @@ struct pm_ctx {
     std::map<std::string, std::vector<int>> tune;  // autotuned (tile_x, tile_y, zc) per shape key
     bool tune_loaded = false;
     pm_stats stats{};
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -177,7 +177,7 @@ void stats_end(pm_ctx *ctx) { ctx->stats.total_ms += now_ms(); }
 
 pm_status ensure_events(pm_ctx *ctx)
 {
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
         if (!ctx->ev[i]) PM_HIP(hipEventCreate(&ctx->ev[i]));
     return PM_OK;
 }
@@ -203,7 +203,9 @@ pm_status check_dims(pm_ctx *ctx, int64_t nx, int64_t ny, int64_t nz)
 {
     if (nx < 1 || ny < 1 || nz < 1) return fail(ctx, PM_ERR_ARG, "dims must be >= 1 (got %lld %lld %lld)",
                                                  (long long)nx, (long long)ny, (long long)nz);
-    if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30) || nx * ny > 0x7fffffffLL ||
+    // a z-plane of a field stays below 2^31 bytes (the sweeps address one plane
+    // of a field with 32-bit byte offsets)
+    if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30) || nx * ny > (int64_t(1) << 28) ||
         nx * ny * nz > (int64_t(1) << 40))
         return fail(ctx, PM_ERR_ARG, "dims too large (%lld %lld %lld)", (long long)nx, (long long)ny,
                     (long long)nz);
@@ -233,6 +235,14 @@ pm_status check_params(pm_ctx *ctx, const pm_params *p)
     if (p->pore_cleanup != 0 && p->pore_cleanup != 1) return fail(ctx, PM_ERR_ARG, "pore_cleanup must be 0 or 1");
     if (p->outer_walls < 0 || p->outer_walls > 7) return fail(ctx, PM_ERR_ARG, "outer_walls must be a bit mask 0..7");
     if (p->dc_form != 0 && p->dc_form != 1) return fail(ctx, PM_ERR_ARG, "dc_form must be 0 or 1");
+    if (p->tblock < 0 || p->tblock > 2) return fail(ctx, PM_ERR_ARG, "tblock must be 0 (auto), 1 or 2");
+    if (p->tile2_x || p->tile2_y) {
+        const bool f64 = p->precision != PM_FP32, f32 = p->precision != PM_FP64;
+        if ((f64 && !fused2_tile_supported(p->tile2_x, p->tile2_y, kF64)) ||
+            (f32 && !fused2_tile_supported(p->tile2_x, p->tile2_y, kF32)))
+            return fail(ctx, PM_ERR_ARG, "unsupported two-sweep tile %dx%d", p->tile2_x, p->tile2_y);
+    }
+    if (p->zchunk2 < 0) return fail(ctx, PM_ERR_ARG, "zchunk2 must be >= 0");
     return PM_OK;
 }
 
@@ -249,7 +259,8 @@ std::string tune_key(int nx, int ny, int nz, Prec prec)
     return std::to_string(nx) + "x" + std::to_string(ny) + "x" + std::to_string(nz) + (prec == kF64 ? ":f64" : ":f32");
 }
 
-// Tuning cache file: a flat JSON object {"NXxNYxNZ:f64": [tx, ty, zc], ...}.
+// Tuning cache file: a flat JSON object {"NXxNYxNZ:f64": [tx, ty, zc, tb, ox, oy, zc2], ...}
+// (entries of three numbers, [tx, ty, zc], are single-step choices).
 void load_tune_cache(pm_ctx *ctx)
 {
     const char *path = std::getenv("PORESTOKES_TUNE_CACHE");
@@ -266,13 +277,24 @@ void load_tune_cache(pm_ctx *ctx)
         size_t k0 = text.find('"', pos);
         if (k0 == std::string::npos) break;
         size_t k1 = text.find('"', k0 + 1);
+        if (k1 == std::string::npos) break;
         size_t b0 = text.find('[', k1);
+        if (b0 == std::string::npos) break;
         size_t b1 = text.find(']', b0);
-        if (k1 == std::string::npos || b0 == std::string::npos || b1 == std::string::npos) break;
-        int tx = 0, ty = 0, zc = 0;
-        if (std::sscanf(text.c_str() + b0, "[%d , %d , %d]", &tx, &ty, &zc) == 3 ||
-            std::sscanf(text.c_str() + b0, "[%d,%d,%d]", &tx, &ty, &zc) == 3)
-            ctx->tune[text.substr(k0 + 1, k1 - k0 - 1)] = {tx, ty, zc};
+        if (b1 == std::string::npos) break;
+        std::vector<int> vals;
+        const char *q = text.c_str() + b0 + 1, *qe = text.c_str() + b1;
+        while (q < qe) {
+            char *end = nullptr;
+            const long v = std::strtol(q, &end, 10);
+            if (end == q) {
+                ++q;
+                continue;
+            }
+            vals.push_back((int)v);
+            q = end;
+        }
+        if (vals.size() == 3 || vals.size() == 7) ctx->tune[text.substr(k0 + 1, k1 - k0 - 1)] = vals;
         pos = b1 + 1;
     }
 }
@@ -287,9 +309,10 @@ void save_tune_cache(const pm_ctx *ctx)
     std::fprintf(f, "{");
     bool first = true;
     for (const auto &kv : ctx->tune) {
-        if (kv.second.size() != 3) continue;
-        std::fprintf(f, "%s\n  \"%s\": [%d, %d, %d]", first ? "" : ",", kv.first.c_str(), kv.second[0],
-                     kv.second[1], kv.second[2]);
+        if (kv.second.size() != 3 && kv.second.size() != 7) continue;
+        std::fprintf(f, "%s\n  \"%s\": [", first ? "" : ",", kv.first.c_str());
+        for (size_t i = 0; i < kv.second.size(); ++i) std::fprintf(f, "%s%d", i ? ", " : "", kv.second[i]);
+        std::fprintf(f, "]");
         first = false;
     }
     std::fprintf(f, "\n}\n");
@@ -300,7 +323,9 @@ void save_tune_cache(const pm_ctx *ctx)
 // ------------------------------------------------------------------ tiles
 
 struct TileCfg {
-    int tx = 64, ty = 8, zc = 32;
+    int tx = 64, ty = 8, zc = 32;      // single-step kernel: tile and z-chunk
+    int tb = 1;                        // sweeps per pass of the bulk launches (1 or 2)
+    int ox = 64, oy = 10, zc2 = 32;    // tb = 2: output tile and z-chunk of the two-step kernel
 };
 
 int auto_zc(int nx, int ny, int nz, int tx, int ty)
@@ -314,19 +339,62 @@ int auto_zc(int nx, int ny, int nz, int tx, int ty)
     int64_t zc = (int64_t)nz * txy * tx * ty / (512LL * 512LL);
     // small grids cannot fill the chip even with 16-plane chunks: there the sweep
     // is latency-bound (one plane after another per workgroup), so shorter chunks
-    // and more workgroups win and the priming bytes do not matter
-    zc = zc < 16 ? std::max<int64_t>(4, zc) : std::min<int64_t>(64, zc);
+    // and more workgroups win and the priming bytes do not matter (32^3, FP64:
+    // 9.5, 7.2 and 6.0 us per sweep with chunks of 4, 2 and 1 planes)
+    zc = zc < 16 ? std::max<int64_t>(1, zc) : std::min<int64_t>(64, zc);
     return (int)std::min<int64_t>(zc, nz);
+}
+
+// z-chunk of the two-step kernel: its workgroups run one per CU (256 at a time)
+// and a chunk of zc planes costs about zc + 5 stage-1 plane steps (the chunk,
+// four planes beyond its ends, the prologue).  Pick the chunk that minimises
+// rounds x steps, the longer chunk on ties.
+int auto_zc2(int nx, int ny, int nz, int ox, int oy)
+{
+    const int64_t txy = (int64_t)((nx + ox - 1) / ox) * ((ny + oy - 1) / oy);
+    int best = std::min(nz, 4);
+    int64_t best_cost = INT64_MAX;
+    for (int zc = 4; zc <= std::min(nz, 64); ++zc) {
+        const int64_t chunks = (nz + zc - 1) / zc;
+        const int64_t rounds = (txy * chunks + 255) / 256;
+        const int64_t cost = rounds * (zc + 5);
+        if (cost <= best_cost) {
+            best_cost = cost;
+            best = zc;
+        }
+    }
+    return std::min(best, nz);
+}
+
+// Default output tile of the two-step kernel: FP32 64 x 10 (68 x 14 threads),
+// FP64 32 x 12 (36 x 16 threads: the FP64 windows of a larger workgroup spill).
+void default_tile2(Prec prec, int *ox, int *oy)
+{
+    if (prec == kF64) {
+        *ox = 32;
+        *oy = 12;
+    } else {
+        *ox = 64;
+        *oy = 10;
+    }
 }
 
 TileCfg pick_tiles(pm_ctx *ctx, const pm_params *prm, int nx, int ny, int nz, Prec prec)
 {
     TileCfg c;
+    default_tile2(prec, &c.ox, &c.oy);
+    c.zc2 = 0;
     auto it = ctx->tune.find(tune_key(nx, ny, nz, prec));
-    if (it != ctx->tune.end() && it->second.size() == 3) {
+    if (it != ctx->tune.end() && (it->second.size() == 3 || it->second.size() == 7)) {
         c.tx = it->second[0];
         c.ty = it->second[1];
         c.zc = it->second[2];
+        if (it->second.size() == 7) {
+            c.tb = it->second[3];
+            c.ox = it->second[4];
+            c.oy = it->second[5];
+            c.zc2 = it->second[6];
+        }
     } else {
         // Measured on MI355X (256^3 packing, three instances per launch):
         // 128x8 in both precisions (FP64 655 us against 654 for 64x16 and 672
@@ -343,6 +411,7 @@ TileCfg pick_tiles(pm_ctx *ctx, const pm_params *prm, int nx, int ny, int nz, Pr
             c.ty = prec == kF64 ? 8 : 16;
         }
         c.zc = 0;
+        c.tb = 1;
     }
     if (prm->tile_x && prm->tile_y) {
         c.tx = prm->tile_x;
@@ -351,6 +420,15 @@ TileCfg pick_tiles(pm_ctx *ctx, const pm_params *prm, int nx, int ny, int nz, Pr
     if (prm->zchunk > 0) c.zc = prm->zchunk;
     if (c.zc <= 0) c.zc = auto_zc(nx, ny, nz, c.tx, c.ty);
     c.zc = std::min(c.zc, nz);
+    if (prm->tblock > 0) c.tb = prm->tblock;
+    if (prm->tile2_x && prm->tile2_y) {
+        c.ox = prm->tile2_x;
+        c.oy = prm->tile2_y;
+    }
+    if (prm->zchunk2 > 0) c.zc2 = prm->zchunk2;
+    if (!fused2_tile_supported(c.ox, c.oy, prec)) default_tile2(prec, &c.ox, &c.oy);
+    if (c.zc2 <= 0) c.zc2 = auto_zc2(nx, ny, nz, c.ox, c.oy);
+    c.zc2 = std::min(c.zc2, nz);
     return c;
 }
 
@@ -377,7 +455,11 @@ struct Inst {
     Prec prec = kF64;
     void *set[2][4] = {};
     void *internal = nullptr;
-    int64_t local_n = 0, sweeps = 0;
+    int64_t sweeps = 0;
+    // launches since the start of the current pipeline (its pressure-passthrough
+    // step included): launch j of a pipeline reads field set j & 1 and writes the
+    // other, whether it advances one sweep or two
+    int64_t passes = 0;
     double rmin = INFINITY, qprev = -1.0;
     int stall = 0, plateau_hits = 0;
     double r_last = INFINITY;
@@ -387,6 +469,7 @@ struct Inst {
     double kcol[3] = {0, 0, 0};
     TileCfg tile;
     int64_t nblocks = 0, partial_rows = 0;
+    int64_t nblocks2 = 0;  // blocks of a two-step launch (tile.tb = 2)
     double *partials = nullptr;
 };
 
@@ -394,6 +477,19 @@ int64_t blocks_of(const Inst &in)
 {
     return (int64_t)((in.nx + in.tile.tx - 1) / in.tile.tx) * ((in.ny + in.tile.ty - 1) / in.tile.ty) *
            ((in.nz + in.tile.zc - 1) / in.tile.zc);
+}
+
+int64_t blocks2_of(const Inst &in)
+{
+    return (int64_t)((in.nx + in.tile.ox - 1) / in.tile.ox) * ((in.ny + in.tile.oy - 1) / in.tile.oy) *
+           ((in.nz + in.tile.zc2 - 1) / in.tile.zc2);
+}
+
+// Whether the bulk launches of an instance advance two sweeps (the two-step
+// kernel has no correction-form variant).
+bool two_step(const Inst &in)
+{
+    return in.tile.tb == 2 && !in.delta && fused2_tile_supported(in.tile.ox, in.tile.oy, in.prec);
 }
 
 size_t elem(Prec p) { return p == kF64 ? sizeof(double) : sizeof(float); }
@@ -405,19 +501,23 @@ bool alone_of(const Inst &in)
     return fused_alone(in.prec, in.tile.tx, in.tile.ty, tiles);
 }
 
-InstDev make_dev(const Inst &in, const pm_params *prm, int64_t blk_begin, bool skip)
+// Table entry of an instance for a single-step launch, or (two) for a
+// two-step launch; launch j of the block reads set (passes + j) & 1.
+InstDev make_dev(const Inst &in, const pm_params *prm, int64_t blk_begin, bool skip, bool two = false)
 {
     InstDev d;
     d.nx = in.nx;
     d.ny = in.ny;
     d.nz = in.nz;
     d.axis = in.axis;
-    d.tiles_x = (in.nx + in.tile.tx - 1) / in.tile.tx;
-    d.tiles_y = (in.ny + in.tile.ty - 1) / in.tile.ty;
-    d.tiles_z = (in.nz + in.tile.zc - 1) / in.tile.zc;
-    d.zc = in.tile.zc;
+    const int tx = two ? in.tile.ox : in.tile.tx, ty = two ? in.tile.oy : in.tile.ty;
+    const int zc = two ? in.tile.zc2 : in.tile.zc;
+    d.tiles_x = (in.nx + tx - 1) / tx;
+    d.tiles_y = (in.ny + ty - 1) / ty;
+    d.tiles_z = (in.nz + zc - 1) / zc;
+    d.zc = zc;
     d.blk_begin = blk_begin;
-    d.nblocks = in.nblocks;
+    d.nblocks = two ? in.nblocks2 : in.nblocks;
     d.codes = in.codes;
     for (int s = 0; s < 2; ++s)
         for (int f = 0; f < 3; ++f) d.vel[s][f] = in.set[s][f];
@@ -428,7 +528,7 @@ InstDev make_dev(const Inst &in, const pm_params *prm, int64_t blk_begin, bool s
     d.dt = prm->dt;
     d.c2dt = prm->c2 * prm->dt;
     d.drive = in.delta ? 0.0 : prm->drive;  // the correction's drive is inside d0
-    d.par_off = skip ? 0 : (int)((in.local_n + 1) & 1);
+    d.par_off = skip ? 0 : (int)(in.passes & 1);
     d.skip = skip ? 1 : 0;
     for (int f = 0; f < 4; ++f)
         d.src[f] = in.delta ? (const char *)in.dsrc + (size_t)f * in.N * sizeof(float) : nullptr;
@@ -498,6 +598,7 @@ struct Engine {
         if (it == batch_tile.end()) return pick_tiles(ctx, prm, in.nx, in.ny, in.nz, p);
         TileCfg c = it->second;
         c.zc = std::min(c.zc, in.nz);
+        c.zc2 = std::min(c.zc2, in.nz);
         return c;
     }
 
@@ -571,6 +672,7 @@ struct Engine {
             }
             in.tile = tile_for(in, in.prec);
             in.nblocks = blocks_of(in);
+            in.nblocks2 = blocks2_of(in);
             if (in.dc) {  // room for the FP64 phase's decomposition too
                 Inst tmp = in;
                 tmp.tile = tile_for(in, kF64);
@@ -591,7 +693,7 @@ struct Engine {
                 }
         }
         void *p = nullptr;
-        PM_TRY(scratch.get(inst.size() * sizeof(InstDev), &p));
+        PM_TRY(scratch.get(2 * inst.size() * sizeof(InstDev), &p));  // single- and two-step entries
         d_tab = (InstDev *)p;
         PM_TRY(scratch.get(inst.size() * sizeof(PartialRef), &p));
         d_refs = (PartialRef *)p;
@@ -617,26 +719,37 @@ struct Engine {
                     PM_HIP(launch_f64_to_f32((const double *)in.user[f], (float *)in.set[0][f], in.N, stream));
             }
             in.needs_start = true;
-            in.local_n = 0;
+            in.passes = 0;
         }
         return PM_OK;
     }
 
     InstDev dev_of(const Inst &in, int64_t blk_begin, bool skip) const { return make_dev(in, prm, blk_begin, skip); }
 
-    // Launch `steps` fused sweeps for the selected instances (reduce on the
-    // last) and bring their sums to ctx->h_sums in selection order.
+    // Advance the selected instances by `steps` sweeps (skip: the one
+    // pressure-passthrough step that starts a pipeline) with the residual sums
+    // of the last one, and bring the sums to ctx->h_sums in selection order.
+    //
+    // Launch plan per group of instances: with the two-step kernel, (steps - 1)
+    // / 2 two-step launches, then one or two single steps; the last launch is
+    // always a single step carrying the reduction, so that the state of the
+    // check, v^n and p^n, is in memory (v^n is the last launch's input).
+    // Otherwise `steps` single steps.
     pm_status run_block(const std::vector<int> &sel, int steps, bool skip)
     {
-        // one sub-table per (precision, tile) group, contiguous in d_tab
+        // one sub-table per (precision, tile) group, contiguous in d_tab; the
+        // two-step entries of the groups that use it follow all single-step ones
         h_tab.clear();
         h_refs.clear();
         struct Group {
             Prec prec;
-            bool src, alone;
-            int tx, ty;
+            bool src, alone, two;
+            int tx, ty, ox, oy;
             int first, count;
             int64_t blocks;
+            int first2;
+            int64_t blocks2;
+            int n2, n1;  // two-step and single-step launches of the plan
         };
         std::vector<Group> groups;
         std::vector<int> order;
@@ -645,35 +758,69 @@ struct Engine {
                 const Inst &in = inst[i];
                 if (pass != (in.prec == kF64 ? 2 : in.delta ? 1 : 0)) continue;
                 const bool alone = alone_of(in);
+                const bool two = !skip && steps >= 3 && two_step(in);
                 if (groups.empty() || groups.back().prec != in.prec || groups.back().src != in.delta ||
-                    groups.back().alone != alone || groups.back().tx != in.tile.tx || groups.back().ty != in.tile.ty)
-                    groups.push_back({in.prec, in.delta, alone, in.tile.tx, in.tile.ty, (int)h_tab.size(), 0, 0});
+                    groups.back().alone != alone || groups.back().tx != in.tile.tx || groups.back().ty != in.tile.ty ||
+                    groups.back().two != two ||
+                    (two && (groups.back().ox != in.tile.ox || groups.back().oy != in.tile.oy)))
+                    groups.push_back({in.prec, in.delta, alone, two, in.tile.tx, in.tile.ty, in.tile.ox, in.tile.oy,
+                                      (int)h_tab.size(), 0, 0, 0, 0, 0, 0});
                 Group &g = groups.back();
                 h_tab.push_back(dev_of(in, g.blocks, skip));
                 g.blocks += in.nblocks;
                 g.count++;
                 order.push_back(i);
             }
+        int64_t vox2 = 0;  // voxel passes of the two-step launches (two sweeps each)
+        for (Group &g : groups) {
+            if (g.two) {
+                g.n2 = (steps - 1) / 2;
+                g.n1 = steps - 2 * g.n2;
+                g.first2 = (int)h_tab.size();
+                for (int k = 0; k < g.count; ++k) {
+                    const Inst &in = inst[order[g.first + k]];
+                    h_tab.push_back(make_dev(in, prm, g.blocks2, false, true));
+                    g.blocks2 += in.nblocks2;
+                    vox2 += in.N * g.n2;
+                }
+            } else {
+                g.n1 = steps;
+            }
+        }
         for (int i : order) h_refs.push_back({inst[i].partials, inst[i].nblocks});
         PM_HIP(hipMemcpyAsync(d_tab, h_tab.data(), h_tab.size() * sizeof(InstDev), hipMemcpyHostToDevice, stream));
         PM_HIP(hipMemcpyAsync(d_refs, h_refs.data(), h_refs.size() * sizeof(PartialRef), hipMemcpyHostToDevice,
                               stream));
         int64_t vox = 0;
         for (int i : order) vox += inst[i].N;
+        int64_t launches = 0, launches2 = 0;
+        for (const Group &g : groups) {
+            launches += g.n1 + g.n2;
+            launches2 += g.n2;
+        }
         PM_TRY(ensure_events(ctx));
-        // the sequence: `steps` sweeps of every group (reduce on the last),
-        // final reduction, copy of the sums to pinned memory.  Timing events
-        // bracket it on the caller's stream (for a graph: around the launch).
-        auto enqueue = [&](hipStream_t st) -> pm_status {
-            for (int j = 0; j < steps; ++j)
-                for (const Group &g : groups) {
-                    const int red = j == steps - 1 ? 1 : 0;
+        // the sequence, in two parts: (a) the two-step launches of every group;
+        // (b) the single steps (reduce on the last), the final reduction, the
+        // copy of the sums to pinned memory.  Launch j of a group reads set
+        // (passes + j) & 1.  Timing events go on the caller's stream before (a),
+        // between the parts and after (b); with graphs each part is one graph.
+        auto enqueue_two = [&](hipStream_t st) -> pm_status {
+            for (const Group &g : groups)
+                for (int j = 0; j < g.n2; ++j)
+                    PM_HIP(launch_fused2(g.prec, g.ox, g.oy, d_tab + g.first2, g.count, g.blocks2, j & 1, st));
+            return PM_OK;
+        };
+        auto enqueue_one = [&](hipStream_t st) -> pm_status {
+            for (const Group &g : groups)
+                for (int k = 0; k < g.n1; ++k) {
+                    const int j = g.n2 + k;
+                    const int red = k == g.n1 - 1 ? 1 : 0;
                     if (g.src)
                         PM_HIP(launch_fused_src(g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1, red, st,
                                                 g.alone));
                     else
-                        PM_HIP(launch_fused(g.prec, g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1, red,
-                                            st, g.alone));
+                        PM_HIP(launch_fused(g.prec, g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1, red, st,
+                                            g.alone));
                 }
             PM_HIP(launch_reduce_partials(d_refs, (int)order.size(), d_sums, st));
             PM_HIP(hipMemcpyAsync(ctx->h_sums, d_sums, order.size() * kNumSums * sizeof(double),
@@ -681,56 +828,85 @@ struct Engine {
             return PM_OK;
         };
         if (prm->graphs && !skip) {
-            std::string key = std::to_string(steps);
+            std::string key;
             for (const Group &g : groups)
                 key += "|" + std::to_string(g.prec) + (g.src ? "s" : "") + (g.alone ? "a" : "") + ":" +
-                       std::to_string(g.tx) + "x" +
-                       std::to_string(g.ty) +
-                       ":" + std::to_string(g.first) + ":" + std::to_string(g.count) + ":" +
-                       std::to_string(g.blocks);
+                       std::to_string(g.tx) + "x" + std::to_string(g.ty) + ":" + std::to_string(g.first) + ":" +
+                       std::to_string(g.count) + ":" + std::to_string(g.blocks) + ":" + std::to_string(g.n1) +
+                       (g.two ? ":2:" + std::to_string(g.ox) + "x" + std::to_string(g.oy) + ":" +
+                                    std::to_string(g.first2) + ":" + std::to_string(g.blocks2) + ":" +
+                                    std::to_string(g.n2)
+                              : "");
             key += "|" + std::to_string(order.size());
-            auto it = graphs.find(key);
-            if (it == graphs.end()) {
-                if (!cap_stream) PM_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
-                PM_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-                pm_status es = enqueue(cap_stream);
-                hipGraph_t g = nullptr;
-                hipError_t ee = hipStreamEndCapture(cap_stream, &g);
-                if (es != PM_OK) {
-                    if (g) (void)hipGraphDestroy(g);
-                    return es;
-                }
-                PM_HIP(ee);
-                hipGraphExec_t ex = nullptr;
-                hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(g);
-                PM_HIP(ei);
-                it = graphs.emplace(key, ex).first;
-            }
+            hipGraphExec_t ex2 = nullptr, ex1 = nullptr;
+            PM_TRY(graph_of("2" + key, enqueue_two, launches2 > 0, &ex2));
+            PM_TRY(graph_of("1" + key, enqueue_one, true, &ex1));
             PM_HIP(hipEventRecord(ctx->ev[0], stream));
-            PM_HIP(hipGraphLaunch(it->second, stream));
+            if (ex2) PM_HIP(hipGraphLaunch(ex2, stream));
+            PM_HIP(hipEventRecord(ctx->ev[2], stream));
+            PM_HIP(hipGraphLaunch(ex1, stream));
             PM_HIP(hipEventRecord(ctx->ev[1], stream));
         } else {
             PM_HIP(hipEventRecord(ctx->ev[0], stream));
-            PM_TRY(enqueue(stream));
+            PM_TRY(enqueue_two(stream));
+            PM_HIP(hipEventRecord(ctx->ev[2], stream));
+            PM_TRY(enqueue_one(stream));
             PM_HIP(hipEventRecord(ctx->ev[1], stream));
         }
         PM_HIP(hipStreamSynchronize(stream));
         {
-            float ms = 0.f;
+            float ms = 0.f, ms2 = 0.f;
             PM_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+            PM_HIP(hipEventElapsedTime(&ms2, ctx->ev[0], ctx->ev[2]));
             ctx->stats.sweep_ms += ms;
-            ctx->stats.sweep_launches += (int64_t)steps * (int64_t)groups.size();
+            ctx->stats.sweep_launches += launches;
             ctx->stats.voxel_updates += vox * steps;
+            if (launches2 > 0) {
+                ctx->stats.t2_ms += ms2;
+                ctx->stats.t2_launches += launches2;
+                ctx->stats.t2_voxels += vox2;
+            }
             const Inst &last = inst[order.back()];
             ctx->stats.tile_x = last.tile.tx;
             ctx->stats.tile_y = last.tile.ty;
             ctx->stats.zchunk = last.tile.zc;
             ctx->stats.precision = last.prec == kF64 ? PM_FP64 : PM_FP32;
+            ctx->stats.tblock = groups.back().two ? 2 : 1;
         }
+        for (const Group &g : groups)
+            for (int k = 0; k < g.count; ++k) inst[order[g.first + k]].passes += g.n1 + g.n2;
         // h_sums rows follow `order`; remap to `sel` positions
         sums_of.assign(inst.size(), nullptr);
         for (size_t r = 0; r < order.size(); ++r) sums_of[order[r]] = ctx->h_sums + r * kNumSums;
+        return PM_OK;
+    }
+
+    // The executable graph captured from `enqueue` under `key` (captured on
+    // first use); none when `want` is false.
+    template <typename F>
+    pm_status graph_of(const std::string &key, F &&enqueue, bool want, hipGraphExec_t *out)
+    {
+        *out = nullptr;
+        if (!want) return PM_OK;
+        auto it = graphs.find(key);
+        if (it == graphs.end()) {
+            if (!cap_stream) PM_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+            PM_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+            pm_status es = enqueue(cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t ee = hipStreamEndCapture(cap_stream, &g);
+            if (es != PM_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return es;
+            }
+            PM_HIP(ee);
+            hipGraphExec_t ex = nullptr;
+            hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            PM_HIP(ei);
+            it = graphs.emplace(key, ex).first;
+        }
+        *out = it->second;
         return PM_OK;
     }
     std::vector<const double *> sums_of;
@@ -753,7 +929,7 @@ struct Engine {
     // Copy the state of the last check into the user fields.
     pm_status finalize(Inst &in)
     {
-        const int vs = (int)(in.local_n & 1), ps_ = (int)((in.local_n + 1) & 1);
+        const int vs = (int)((in.passes - 1) & 1), ps_ = (int)(in.passes & 1);
         const size_t e = elem(in.prec);
         // in the final phase set 0 is the user set (FP64, FP32) -- for FP32_DC the
         // FP32 phase never finalises with status OK, but may with an error status
@@ -779,7 +955,7 @@ struct Engine {
     // s0 + e into the user fields (FP64) at the end of the correction form
     pm_status fold_correction(Inst &in)
     {
-        const int vs = (int)(in.local_n & 1), ps_ = (int)((in.local_n + 1) & 1);
+        const int vs = (int)((in.passes - 1) & 1), ps_ = (int)(in.passes & 1);
         for (int f = 0; f < 3; ++f)
             PM_HIP(launch_add_f32_to_f64((const float *)in.set[vs][f], (double *)in.user[f], in.N, stream));
         PM_HIP(launch_add_f32_to_f64((const float *)in.set[ps_][3], (double *)in.user[3], in.N, stream));
@@ -793,7 +969,8 @@ struct Engine {
     void restart_phase(Inst &in)
     {
         in.nblocks = blocks_of(in);
-        in.local_n = 0;
+        in.nblocks2 = blocks2_of(in);
+        in.passes = 0;
         in.needs_start = true;
         in.rmin = INFINITY;
         in.stall = 0;
@@ -808,7 +985,7 @@ struct Engine {
         if (in.delta) {
             PM_TRY(fold_correction(in));
         } else {
-            const int vs = (int)(in.local_n & 1), ps_ = (int)((in.local_n + 1) & 1);
+            const int vs = (int)((in.passes - 1) & 1), ps_ = (int)(in.passes & 1);
             for (int f = 0; f < 3; ++f)
                 PM_HIP(launch_f32_to_f64((const float *)in.set[vs][f], (double *)in.user[f], in.N, stream));
             PM_HIP(launch_f32_to_f64((const float *)in.set[ps_][3], (double *)in.user[3], in.N, stream));
@@ -838,11 +1015,12 @@ struct Engine {
             void *p = nullptr;
             if (scratch.get(4 * (size_t)in.N * sizeof(float), &p) != PM_OK) {
                 ctx->err.clear();
+                ctx->stats.dc_promoted_for_memory++;
                 return promote(in);
             }
             in.dsrc = p;
         }
-        const int vs = (int)(in.local_n & 1), ps_ = (int)((in.local_n + 1) & 1);
+        const int vs = (int)((in.passes - 1) & 1), ps_ = (int)(in.passes & 1);
         for (int f = 0; f < 3; ++f)
             PM_HIP(launch_f32_to_f64((const float *)in.set[vs][f], (double *)in.user[f], in.N, stream));
         PM_HIP(launch_f32_to_f64((const float *)in.set[ps_][3], (double *)in.user[3], in.N, stream));
@@ -854,7 +1032,7 @@ struct Engine {
         in.tile = tile_for(in, kF64);
         in.nblocks = blocks_of(in);
         if (in.nblocks > in.partial_rows) return fail(ctx, PM_ERR_ARG, "internal: block count grew on promotion");
-        in.local_n = 1;  // the full update, reading set 0
+        in.passes = 0;  // the full update, reading set 0 (passes is reset with the phase below)
         PM_TRY(run_block({i}, 1, false));
         for (int k = 0; k < 3; ++k) in.q0[k] = sums_of[i][2 + k];
         for (int f = 0; f < 4; ++f)
@@ -1006,7 +1184,6 @@ struct Engine {
             PM_TRY(run_block(actives, steps, false));
             double rworst = 0.0;
             for (int i : actives) {
-                inst[i].local_n += steps;
                 inst[i].sweeps += steps;
                 PM_TRY(check(inst[i], sums_of[i]));
                 rworst = std::max(rworst, inst[i].r_last);
@@ -1026,7 +1203,10 @@ struct Engine {
 };
 
 // Time every supported decomposition of the fused sweep on one shape and
-// precision (from rest, on scratch fields) and keep the fastest.
+// precision (from rest, on scratch fields) and keep the fastest: the
+// single-step tiles and z-chunks, then the two-step tiles and z-chunks, each
+// priced per sweep.  The single-step choice is kept either way (the first
+// step of a pipeline and the checked steps are single steps).
 pm_status autotune_shape(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx, int ny, int nz, Prec prec,
                          TileCfg *best_out)
 {
@@ -1035,12 +1215,17 @@ pm_status autotune_shape(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx
     void *codes = nullptr, *fields = nullptr, *tab = nullptr, *part = nullptr;
     PM_TRY(scratch.get((size_t)N * sizeof(uint32_t), &codes));
     PM_TRY(scratch.get(8 * (size_t)N * elem(prec), &fields));
-    PM_TRY(scratch.get(2 * sizeof(InstDev), &tab));
+    PM_TRY(scratch.get(3 * sizeof(InstDev), &tab));
     PM_HIP(launch_face_codes(mask, nx, ny, nz, (uint32_t *)codes, s));
     PM_HIP(hipMemsetAsync(fields, 0, 4 * (size_t)N * elem(prec), s));
     const int tiles[5][2] = {{128, 8}, {64, 8}, {32, 8}, {32, 16}, {64, 16}};
+    const int tiles2[6][2] = {{64, 10}, {64, 8}, {64, 6}, {32, 24}, {32, 12}, {32, 8}};
     const int zcs[4] = {16, 32, 64, 128};
-    std::vector<TileCfg> cands;
+    struct Cand {
+        TileCfg c;
+        bool two;
+    };
+    std::vector<Cand> cands;
     for (auto &t : tiles) {
         if (!fused_tile_supported(t[0], t[1], prec)) continue;
         int last = -1;
@@ -1052,27 +1237,45 @@ pm_status autotune_shape(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx
             c.tx = t[0];
             c.ty = t[1];
             c.zc = z;
-            cands.push_back(c);
+            cands.push_back({c, false});
+        }
+    }
+    for (auto &t : tiles2) {
+        if (!fused2_tile_supported(t[0], t[1], prec)) continue;
+        std::vector<int> zc2s = {auto_zc2(nx, ny, nz, t[0], t[1]), 16, 32, 64};
+        std::sort(zc2s.begin(), zc2s.end());
+        int last = -1;
+        for (int zc : zc2s) {
+            const int z = std::min(zc, nz);
+            if (z == last) continue;
+            last = z;
+            TileCfg c;
+            c.tb = 2;
+            c.ox = t[0];
+            c.oy = t[1];
+            c.zc2 = z;
+            cands.push_back({c, true});
         }
     }
     int64_t maxb = 0;
-    for (const TileCfg &c : cands) {
+    for (const Cand &k : cands) {
         Inst in;
         in.nx = nx;
         in.ny = ny;
         in.nz = nz;
-        in.tile = c;
-        maxb = std::max(maxb, blocks_of(in));
+        in.tile = k.c;
+        maxb = std::max(maxb, k.two ? blocks2_of(in) : blocks_of(in));
     }
     PM_TRY(scratch.get((size_t)maxb * kNumSums * sizeof(double), &part));
     pm_params prm;
     pm_params_default(&prm);
-    // timed sweeps per candidate: ~2e9 voxel updates, at least 3
+    // timed launches per candidate: ~2e9 voxel passes, at least 3
     const int reps = (int)std::max<int64_t>(3, std::min<int64_t>(20, (int64_t)2000000000 / std::max<int64_t>(N, 1)));
     PM_TRY(ensure_events(ctx));
-    float best_ms = INFINITY;
-    TileCfg best = cands.front();
-    for (const TileCfg &c : cands) {
+    float best1_ms = INFINITY, best2_ms = INFINITY;  // per sweep
+    TileCfg best1 = cands.front().c, best2;
+    bool have2 = false;
+    for (const Cand &k : cands) {
         Inst in;
         in.nx = nx;
         in.ny = ny;
@@ -1080,33 +1283,63 @@ pm_status autotune_shape(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx
         in.N = N;
         in.codes = (uint32_t *)codes;
         in.prec = prec;
-        for (int k = 0; k < 4; ++k) {
-            in.set[0][k] = (char *)fields + (size_t)k * N * elem(prec);
-            in.set[1][k] = (char *)fields + (size_t)(4 + k) * N * elem(prec);
+        for (int f = 0; f < 4; ++f) {
+            in.set[0][f] = (char *)fields + (size_t)f * N * elem(prec);
+            in.set[1][f] = (char *)fields + (size_t)(4 + f) * N * elem(prec);
         }
-        in.tile = c;
+        in.tile = k.two ? best1 : k.c;  // the two-step candidates start from the best single-step tile
+        if (k.two) {
+            in.tile.tb = 2;
+            in.tile.ox = k.c.ox;
+            in.tile.oy = k.c.oy;
+            in.tile.zc2 = k.c.zc2;
+        }
         in.nblocks = blocks_of(in);
+        in.nblocks2 = blocks2_of(in);
         in.partials = (double *)part;
-        InstDev d[2] = {make_dev(in, &prm, 0, true), make_dev(in, &prm, 0, false)};
-        d[1].par_off = 1;
-        PM_HIP(hipMemcpyAsync(tab, d, sizeof d, hipMemcpyHostToDevice, s));
+        InstDev d[3] = {make_dev(in, &prm, 0, true), make_dev(in, &prm, 0, false),
+                        make_dev(in, &prm, 0, false, true)};
+        PM_HIP(launch_store_insts(d, 3, (InstDev *)tab, s));
         InstDev *dt = (InstDev *)tab;
         const bool alone = alone_of(in);
-        PM_HIP(launch_fused(prec, c.tx, c.ty, dt, 1, in.nblocks, 0, 0, s, alone));
-        PM_HIP(launch_fused(prec, c.tx, c.ty, dt + 1, 1, in.nblocks, 0, 0, s, alone));
+        PM_HIP(launch_fused(prec, in.tile.tx, in.tile.ty, dt, 1, in.nblocks, 0, 0, s, alone));
+        if (k.two)
+            PM_HIP(launch_fused2(prec, in.tile.ox, in.tile.oy, dt + 2, 1, in.nblocks2, 1, s));
+        else
+            PM_HIP(launch_fused(prec, in.tile.tx, in.tile.ty, dt + 1, 1, in.nblocks, 1, 0, s, alone));
         PM_HIP(hipEventRecord(ctx->ev[0], s));
-        for (int r = 0; r < reps; ++r)
-            PM_HIP(launch_fused(prec, c.tx, c.ty, dt + 1, 1, in.nblocks, (r + 1) & 1, 0, s, alone));
+        for (int r = 0; r < reps; ++r) {
+            if (k.two)
+                PM_HIP(launch_fused2(prec, in.tile.ox, in.tile.oy, dt + 2, 1, in.nblocks2, r & 1, s));
+            else
+                PM_HIP(launch_fused(prec, in.tile.tx, in.tile.ty, dt + 1, 1, in.nblocks, r & 1, 0, s, alone));
+        }
         PM_HIP(hipEventRecord(ctx->ev[1], s));
         PM_HIP(hipEventSynchronize(ctx->ev[1]));
         float ms = 0.f;
         PM_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = c;
+        const float per_sweep = ms / (k.two ? 2.0f : 1.0f);
+        if (!k.two && per_sweep < best1_ms) {
+            best1_ms = per_sweep;
+            best1 = k.c;
+        }
+        if (k.two && per_sweep < best2_ms) {
+            best2_ms = per_sweep;
+            best2 = in.tile;
+            have2 = true;
         }
     }
-    ctx->tune[tune_key(nx, ny, nz, prec)] = {best.tx, best.ty, best.zc};
+    TileCfg best = best1;
+    best.tb = 1;
+    default_tile2(prec, &best.ox, &best.oy);
+    best.zc2 = auto_zc2(nx, ny, nz, best.ox, best.oy);
+    if (have2) {
+        best.ox = best2.ox;
+        best.oy = best2.oy;
+        best.zc2 = best2.zc2;
+        if (best2_ms < best1_ms) best.tb = 2;
+    }
+    ctx->tune[tune_key(nx, ny, nz, prec)] = {best.tx, best.ty, best.zc, best.tb, best.ox, best.oy, best.zc2};
     save_tune_cache(ctx);
     if (best_out) *best_out = best;
     return PM_OK;
@@ -1303,6 +1536,122 @@ pm_status pore_flow(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx, int
 
 // ====================================================================== ABI
 
+namespace {
+
+// The sweeps of pm_iterate on buffers the caller of this routine provides:
+// codes (N uint32), second (4 N values of the precision), tab (2 InstDev).
+// timed: record HIP events around the sweeps into ctx->stats.  Every buffer
+// is written before it is read: the codes by the preprocessing kernel, the
+// second set by the first sweep launch, the table by its store kernel.
+pm_status iterate_on(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx, int ny, int nz, int axis,
+                     const pm_params *params, void *const f[4], int64_t count, void *codes, void *second,
+                     InstDev *tab, bool timed)
+{
+    const Prec prec = params->precision == PM_FP64 ? kF64 : kF32;
+    const int64_t N = (int64_t)nx * ny * nz;
+    PM_HIP(launch_face_codes(mask, nx, ny, nz, (uint32_t *)codes, s));
+    PM_HIP(launch_zero_solid(prec, (const uint32_t *)codes, N, f[0], f[1], f[2], s));
+    void *set[2][4];
+    for (int k = 0; k < 4; ++k) {
+        set[0][k] = f[k];
+        set[1][k] = (char *)second + (size_t)k * N * elem(prec);
+    }
+    const double nu = 1.0 / params->re, c2dt = params->c2 * params->dt;
+    if (params->kernel == PM_KERNEL_SIMPLE) {
+        if (timed) PM_TRY(stats_mark(ctx, s, true));
+        for (int64_t n = 0; n < count; ++n) {
+            const int a = (int)(n & 1);
+            PM_HIP(launch_simple_sweep(prec, nx, ny, nz, axis, (const uint32_t *)codes, set[a], set[a ^ 1], nu,
+                                       params->dt, c2dt, params->drive, s));
+        }
+        if (timed) PM_TRY(stats_mark(ctx, s, false, 2 * count, count * N));
+        if (count & 1)
+            for (int k = 0; k < 4; ++k)
+                PM_HIP(hipMemcpyAsync(f[k], set[1][k], (size_t)N * elem(prec), hipMemcpyDeviceToDevice, s));
+        return PM_OK;
+    }
+    // fused: K_0 (pressure passthrough), then `count` steps; the state after
+    // them is v^count (the last launch's input set) and p^count (its output).
+    // With the two-step kernel, (count - 1) / 2 two-step launches come first,
+    // then single steps, so that the last launch is a single step.  Launch j
+    // reads set j & 1 whether it advances one sweep or two.
+    Inst in;
+    in.nx = nx;
+    in.ny = ny;
+    in.nz = nz;
+    in.axis = axis;
+    in.N = N;
+    in.codes = (uint32_t *)codes;
+    in.prec = prec;
+    for (int k = 0; k < 4; ++k) {
+        in.set[0][k] = set[0][k];
+        in.set[1][k] = set[1][k];
+    }
+    in.tile = pick_tiles(ctx, params, in.nx, in.ny, in.nz, prec);
+    in.nblocks = blocks_of(in);
+    in.nblocks2 = blocks2_of(in);
+    in.partials = nullptr;  // launches without the reduction never touch it
+    const bool two = two_step(in);
+    const int64_t n2 = two ? (count - 1) / 2 : 0, n1 = count - 2 * n2;
+    InstDev d[3] = {make_dev(in, params, 0, true), make_dev(in, params, 0, false),
+                    make_dev(in, params, 0, false, true)};
+    PM_HIP(launch_store_insts(d, 3, tab, s));
+    if (timed) {
+        PM_TRY(ensure_events(ctx));
+        PM_HIP(hipEventRecord(ctx->ev[0], s));
+    }
+    const bool alone = alone_of(in);
+    int64_t j = 0;
+    PM_HIP(launch_fused(prec, in.tile.tx, in.tile.ty, tab, 1, in.nblocks, 0, 0, s, alone));
+    ++j;
+    if (timed) PM_HIP(hipEventRecord(ctx->ev[2], s));
+    for (int64_t k = 0; k < n2; ++k, ++j)
+        PM_HIP(launch_fused2(prec, in.tile.ox, in.tile.oy, tab + 2, 1, in.nblocks2, (int)(j & 1), s));
+    if (timed) PM_HIP(hipEventRecord(ctx->ev[3], s));
+    for (int64_t k = 0; k < n1; ++k, ++j)
+        PM_HIP(launch_fused(prec, in.tile.tx, in.tile.ty, tab + 1, 1, in.nblocks, (int)(j & 1), 0, s, alone));
+    if (timed) {
+        PM_HIP(hipEventRecord(ctx->ev[1], s));
+        PM_HIP(hipEventSynchronize(ctx->ev[1]));
+        float ms = 0.f, ms2 = 0.f;
+        PM_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+        PM_HIP(hipEventElapsedTime(&ms2, ctx->ev[2], ctx->ev[3]));
+        ctx->stats.sweep_ms += ms;
+        ctx->stats.sweep_launches += j;
+        ctx->stats.voxel_updates += (count + 1) * N;
+        ctx->stats.t2_launches += n2;
+        ctx->stats.t2_voxels += n2 * N;
+        ctx->stats.t2_ms += n2 ? ms2 : 0.0;
+        ctx->stats.tile_x = in.tile.tx;
+        ctx->stats.tile_y = in.tile.ty;
+        ctx->stats.zchunk = in.tile.zc;
+        ctx->stats.precision = prec == kF64 ? PM_FP64 : PM_FP32;
+        ctx->stats.tblock = two ? 2 : 1;
+    }
+    // launch j - 1 was the last: v^count in set (j - 1) & 1, p^count in set j & 1
+    const int vs = (int)((j - 1) & 1), ps_ = (int)(j & 1);
+    if (vs)
+        for (int k = 0; k < 3; ++k)
+            PM_HIP(hipMemcpyAsync(f[k], set[1][k], (size_t)N * elem(prec), hipMemcpyDeviceToDevice, s));
+    if (ps_) PM_HIP(hipMemcpyAsync(f[3], set[1][3], (size_t)N * elem(prec), hipMemcpyDeviceToDevice, s));
+    return PM_OK;
+}
+
+pm_status check_iterate_args(pm_ctx *ctx, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz, int axis,
+                             const pm_params *params, void *const f[4], int64_t count)
+{
+    PM_TRY(check_params(ctx, params));
+    if (params->precision == PM_FP32_DC) return fail(ctx, PM_ERR_ARG, "pm_iterate takes PM_FP64 or PM_FP32");
+    if (params->outer_walls)
+        return fail(ctx, PM_ERR_ARG, "outer_walls applies to solves (pm_solve, pm_tensor, pm_solve_batch)");
+    const Prec prec = params->precision == PM_FP64 ? kF64 : kF32;
+    PM_TRY(check_instance_args(ctx, mask, nx, ny, nz, axis, 1.0, 1.0, f, true, elem(prec)));
+    if (count < 0) return fail(ctx, PM_ERR_ARG, "count must be >= 0");
+    return PM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void pm_params_default(pm_params *p)
@@ -1406,7 +1755,7 @@ void pm_destroy(pm_ctx *ctx)
 {
     if (!ctx) return;
     (void)hipSetDevice(ctx->dev);
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     for (auto &kv : ctx->allocs) (void)hipFree(kv.first);
     release_pool(ctx);
@@ -1458,84 +1807,21 @@ pm_status pm_iterate(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx,
 {
     if (!ctx) return PM_ERR_ARG;
     ctx->err.clear();
-    PM_TRY(check_params(ctx, params));
-    if (params->precision == PM_FP32_DC) return fail(ctx, PM_ERR_ARG, "pm_iterate takes PM_FP64 or PM_FP32");
-    if (params->outer_walls) return fail(ctx, PM_ERR_ARG, "outer_walls applies to solves (pm_solve, pm_tensor, pm_solve_batch)");
-    const Prec prec = params->precision == PM_FP64 ? kF64 : kF32;
     void *f[4] = {u, v, w, p};
-    PM_TRY(check_instance_args(ctx, mask, nx, ny, nz, axis, 1.0, 1.0, f, true, elem(prec)));
-    if (count < 0) return fail(ctx, PM_ERR_ARG, "count must be >= 0");
+    PM_TRY(check_iterate_args(ctx, mask, nx, ny, nz, axis, params, f, count));
     PM_TRY(set_device(ctx));
     hipStream_t s = (hipStream_t)stream;
     stats_begin(ctx);
     if (count == 0) return PM_OK;
+    const Prec prec = params->precision == PM_FP64 ? kF64 : kF32;
     const int64_t N = nx * ny * nz;
     Scratch scratch(ctx);
-    void *codes = nullptr, *second = nullptr;
+    void *codes = nullptr, *second = nullptr, *tab = nullptr;
     PM_TRY(scratch.get((size_t)N * 4, &codes));
     PM_TRY(scratch.get(4 * (size_t)N * elem(prec), &second));
-    PM_HIP(launch_face_codes(mask, (int)nx, (int)ny, (int)nz, (uint32_t *)codes, s));
-    PM_HIP(launch_zero_solid(prec, (const uint32_t *)codes, N, u, v, w, s));
-    void *set[2][4];
-    for (int k = 0; k < 4; ++k) {
-        set[0][k] = f[k];
-        set[1][k] = (char *)second + (size_t)k * N * elem(prec);
-    }
-    const double nu = 1.0 / params->re, c2dt = params->c2 * params->dt;
-    if (params->kernel == PM_KERNEL_SIMPLE) {
-        PM_TRY(stats_mark(ctx, s, true));
-        for (int64_t n = 0; n < count; ++n) {
-            const int a = (int)(n & 1);
-            PM_HIP(launch_simple_sweep(prec, (int)nx, (int)ny, (int)nz, axis, (const uint32_t *)codes, set[a],
-                                       set[a ^ 1], nu, params->dt, c2dt, params->drive, s));
-        }
-        PM_TRY(stats_mark(ctx, s, false, 2 * count, count * N));
-        if (count & 1)
-            for (int k = 0; k < 4; ++k)
-                PM_HIP(hipMemcpyAsync(f[k], set[1][k], (size_t)N * elem(prec), hipMemcpyDeviceToDevice, s));
-        return PM_OK;
-    }
-    // fused: launches K_0 (pressure passthrough) .. K_count; state count is
-    // v^count (set count&1) and p^count (set (count+1)&1)
-    Inst in;
-    in.nx = (int)nx;
-    in.ny = (int)ny;
-    in.nz = (int)nz;
-    in.axis = axis;
-    in.N = N;
-    in.codes = (uint32_t *)codes;
-    in.prec = prec;
-    for (int k = 0; k < 4; ++k) {
-        in.set[0][k] = set[0][k];
-        in.set[1][k] = set[1][k];
-    }
-    in.tile = pick_tiles(ctx, params, in.nx, in.ny, in.nz, prec);
-    in.nblocks = blocks_of(in);
-    void *part = nullptr, *tab = nullptr;
-    PM_TRY(scratch.get((size_t)in.nblocks * kNumSums * sizeof(double), &part));
-    PM_TRY(scratch.get(2 * sizeof(InstDev), &tab));
-    in.partials = (double *)part;
-    std::vector<Inst> one(1, in);
-    Engine eng(ctx, s, params, one);
-    InstDev d[2] = {eng.dev_of(in, 0, true), eng.dev_of(in, 0, false)};
-    d[1].par_off = 1;  // sweeps K_1.. read set (n & 1) with launch parity j & 1 for n = j + 1
-    PM_HIP(hipMemcpyAsync(tab, d, sizeof d, hipMemcpyHostToDevice, s));
-    InstDev *dt = (InstDev *)tab;
-    PM_TRY(stats_mark(ctx, s, true));
-    const bool alone = alone_of(in);
-    PM_HIP(launch_fused(prec, in.tile.tx, in.tile.ty, dt, 1, in.nblocks, 0, 0, s, alone));
-    for (int64_t n = 1; n <= count; ++n)
-        PM_HIP(launch_fused(prec, in.tile.tx, in.tile.ty, dt + 1, 1, in.nblocks, (int)((n - 1) & 1), 0, s, alone));
-    PM_TRY(stats_mark(ctx, s, false, count + 1, (count + 1) * N));
-    ctx->stats.tile_x = in.tile.tx;
-    ctx->stats.tile_y = in.tile.ty;
-    ctx->stats.zchunk = in.tile.zc;
-    ctx->stats.precision = prec == kF64 ? PM_FP64 : PM_FP32;
-    const int vs = (int)(count & 1), ps_ = (int)((count + 1) & 1);
-    if (vs)
-        for (int k = 0; k < 3; ++k)
-            PM_HIP(hipMemcpyAsync(f[k], set[1][k], (size_t)N * elem(prec), hipMemcpyDeviceToDevice, s));
-    if (ps_) PM_HIP(hipMemcpyAsync(f[3], set[1][3], (size_t)N * elem(prec), hipMemcpyDeviceToDevice, s));
+    PM_TRY(scratch.get(3 * sizeof(InstDev), &tab));
+    PM_TRY(iterate_on(ctx, s, mask, (int)nx, (int)ny, (int)nz, axis, params, f, count, codes, second,
+                      (InstDev *)tab, true));
     // the scratch buffers are freed on return: finish the work that reads them
     PM_HIP(hipStreamSynchronize(s));
     stats_end(ctx);
@@ -1577,7 +1863,7 @@ pm_status pm_residual(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx
 }
 
 pm_status pm_autotune(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz,
-                      int precision, int32_t best[3])
+                      int precision, int32_t best[7])
 {
     if (!ctx) return PM_ERR_ARG;
     ctx->err.clear();
@@ -1593,6 +1879,10 @@ pm_status pm_autotune(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx
         best[0] = c.tx;
         best[1] = c.ty;
         best[2] = c.zc;
+        best[3] = c.tb;
+        best[4] = c.ox;
+        best[5] = c.oy;
+        best[6] = c.zc2;
     }
     return PM_OK;
 }
@@ -1799,8 +2089,58 @@ pm_status pm_tensor(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, 
         in[j].axis = j;
         in[j].hist = hist ? &hist[j] : nullptr;
     }
-    if (params && params->warm_start) return fail(ctx, PM_ERR_ARG, "pm_tensor keeps its fields internally");
-    pm_status s = pm_solve_batch(ctx, stream, in, 3, params);
+    PM_TRY(check_params(ctx, params));
+    if (params->warm_start) return fail(ctx, PM_ERR_ARG, "pm_tensor keeps its fields internally");
+    PM_TRY(check_dims(ctx, nx, ny, nz));
+    PM_TRY(set_device(ctx));
+    // The three load cases run as one batch when their buffers fit beside each
+    // other (the context cap and the device's free memory, kept blocks counted
+    // as free), else one after another: each solve's iterate is the same either
+    // way (an untuned batch decomposes every instance as its single solve).
+    bool together = true;
+    {
+        const int64_t N = nx * ny * nz;
+        const size_t ue = params->precision == PM_FP32 ? sizeof(float) : sizeof(double);
+        // stencil codes once, per load case caller-set and internal set (and the
+        // correction form's defect field), rounded up for padding by outer walls
+        const size_t per_case = 8 * (size_t)N * ue + (params->precision == PM_FP32_DC ? 16 * (size_t)N : 0);
+        const size_t need = (size_t)(1.02 * (double)(4 * (size_t)N + 3 * per_case));
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            (void)hipGetLastError();
+            free_b = SIZE_MAX / 2;
+        }
+        size_t avail = free_b + ctx->pooled;
+        if (ctx->cap) avail = std::min(avail, ctx->cap > ctx->used ? ctx->cap - ctx->used : (size_t)0);
+        together = need <= avail;
+    }
+    pm_status s;
+    if (together) {
+        s = pm_solve_batch(ctx, stream, in, 3, params);
+        ctx->stats.tensor_cases_at_once = 3;
+    } else {
+        pm_stats sum{};
+        s = PM_OK;
+        for (int j = 0; j < 3; ++j) {
+            const pm_status sj = pm_solve_batch(ctx, stream, &in[j], 1, params);
+            const pm_stats &st = ctx->stats;
+            sum.sweep_launches += st.sweep_launches;
+            sum.voxel_updates += st.voxel_updates;
+            sum.sweep_ms += st.sweep_ms;
+            sum.total_ms += st.total_ms;
+            sum.tile_x = st.tile_x;
+            sum.tile_y = st.tile_y;
+            sum.zchunk = st.zchunk;
+            sum.precision = st.precision;
+            sum.tblock = st.tblock;
+            sum.peak_bytes = std::max(sum.peak_bytes, st.peak_bytes);
+            sum.dc_promoted_for_memory += st.dc_promoted_for_memory;
+            if (severity(sj) > severity(s)) s = sj;
+            if (sj == PM_ERR_ARG || sj == PM_ERR_OOM || sj == PM_ERR_DEVICE) break;
+        }
+        sum.tensor_cases_at_once = 1;
+        ctx->stats = sum;
+    }
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) k[i * 3 + j] = in[j].k_col[i];
     for (int i = 0; i < 3; ++i)

@@ -29,6 +29,10 @@ struct InstDev {
     double rdt, rc2dt;
 };
 
+// Write n <= 3 table entries to device memory from the launch arguments (no
+// host buffer involved).
+hipError_t launch_store_insts(const InstDev *h, int n, InstDev *dst, hipStream_t s);
+
 // Reference to one instance's block partials for the final reduction.
 struct PartialRef {
     const double *partials;
@@ -72,6 +76,12 @@ hipError_t launch_fused(Prec prec, int tile_x, int tile_y, const InstDev *insts,
 // The same sweep in FP32 with the correction-form terms of InstDev::src.
 hipError_t launch_fused_src(int tile_x, int tile_y, const InstDev *insts, int ninst, int64_t nblocks, int parity,
                             int reduce, hipStream_t s, bool alone = false);
+// Two fused steps per launch over output tiles of ox x oy columns (workgroups
+// of (ox + 4) x (oy + 4) threads); never reducing, never skipping.  The table
+// entries carry the decomposition of these tiles.
+hipError_t launch_fused2(Prec prec, int ox, int oy, const InstDev *insts, int ninst, int64_t nblocks, int parity,
+                         hipStream_t s);
+bool fused2_tile_supported(int ox, int oy, int prec);
 // Whether a sweep of this precision and tile over planes of tiles_per_plane
 // tiles runs one workgroup per CU: FP32 1024-thread tiles on planes of at least
 // 1024 tiles measured 5-8 % faster so (1024^3, 1536^3) and 0 to -3.5 % on

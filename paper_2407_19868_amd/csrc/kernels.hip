@@ -8,6 +8,8 @@
 #include "common.h"
 #include "kernels.h"
 
+#include <cstring>
+
 #define GLOBAL_AS __attribute__((address_space(1)))
 
 namespace ps {
@@ -148,6 +150,26 @@ __global__ void k_defect(const double *__restrict__ t_, const double *__restrict
 }
 
 static inline unsigned grid1d(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+struct InstTriple {
+    InstDev d[3];
+};
+
+__global__ void k_store_insts(InstTriple p, int n, InstDev *__restrict__ dst)
+{
+    if (threadIdx.x == 0)
+        for (int i = 0; i < n; ++i) dst[i] = p.d[i];
+}
+
+hipError_t launch_store_insts(const InstDev *h, int n, InstDev *dst, hipStream_t s)
+{
+    if (n < 1 || n > 3) return hipErrorInvalidValue;
+    InstTriple p;
+    std::memset(&p, 0, sizeof p);
+    for (int i = 0; i < n; ++i) p.d[i] = h[i];
+    hipLaunchKernelGGL(k_store_insts, dim3(1), dim3(64), 0, s, p, n, dst);
+    return hipGetLastError();
+}
 
 hipError_t launch_face_bits(const uint8_t *mask, int nx, int ny, int nz, uint32_t *bits, hipStream_t s)
 {
@@ -334,27 +356,33 @@ hipError_t launch_defect(const double *t, const double *s0, float *d, int64_t n,
 // loads are non-temporal, leaving L2 to the planes that neighbouring tiles
 // read again as halo.
 
-// The far-wall coefficient of App. B (-1/5, on v[+2] when the near wall is
-// at -1, on v[-2] when it is at +1) is nonzero for exactly two codes, so the
-// LDS table holds (a, b) only -- one 16-byte read per lookup in FP64 instead
-// of two -- and gp, gm come from two compares.  Same values, same operation
-// order as d2_perp: the result is bitwise the same.
+// The App. B coefficients of each 3-bit code sit in LDS as (a, b, gp, gm): one
+// 4-wide read per lookup (one 16-byte read in FP32, two in FP64).  The far-wall
+// coefficient (-1/5, on v[+2] when the near wall is at -1, on v[-2] when it is
+// at +1) is nonzero for two codes only.  Same values, same operation order as
+// d2_perp: the result is bitwise the same.
 template <typename T>
-struct CoefAB {
-    T a, b;
+struct alignas(4 * sizeof(T)) Coef4 {
+    T a, b, gp, gm;
 };
 
 template <typename T>
-__device__ __forceinline__ T d2_perp_tab(const CoefAB<T> *tab, uint32_t c, T vm2, T vm1, T v0, T vp1, T vp2)
+__device__ __forceinline__ T d2_perp_t4(const Coef4<T> *tab, uint32_t c, T vm2, T vm1, T v0, T vp1, T vp2)
 {
-    const CoefAB<T> ab = tab[c];
-    const T far = -(T(1) / T(5));
-    const T gp = c == 1u ? far : T(0);
-    const T gm = c == 2u ? far : T(0);
-    T t = gm * vm2;
-    t = fma(gp, vp2, t);
-    t = fma(ab.b, v0, t);
-    return fma(ab.a, vm1 + vp1, t);
+    const Coef4<T> k = tab[c];
+    T t = k.gm * vm2;
+    t = fma(k.gp, vp2, t);
+    t = fma(k.b, v0, t);
+    return fma(k.a, vm1 + vp1, t);
+}
+
+template <typename T>
+__device__ __forceinline__ void fill_coef4(Coef4<T> *tab, int tid)
+{
+    if (tid < 8) {
+        const Coef<T> c8 = coef_of_code<T>(tid);
+        tab[tid] = {c8.a, c8.b, c8.gp, c8.gm};
+    }
 }
 
 template <bool B>
@@ -366,6 +394,47 @@ struct BoolC {
 constexpr int kNumXcd = 8;
 constexpr int kCusPerXcd = 32;
 
+// ---- raw buffer access (MUBUF).  The sweeps address one z-plane of a field
+// at a time: a descriptor with the plane's base (uniform, built in scalar
+// registers) and the plane's byte size as its range, plus a 32-bit per-lane
+// byte offset that stays fixed along the column.  An offset at or beyond the
+// range reads 0 and drops a store (the hardware's range check).
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9 word 3: 32-bit data format, untyped access
+constexpr int kNonTemporal = 2;         // cache policy bit: nt
+constexpr uint32_t kOffNone = 0x80000000u;  // beyond every plane (planes hold < 2^31 bytes)
+using Rsrc = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ Rsrc rsrc_at(const void *base, int64_t off_b, uint32_t nbytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)((const char *)base + off_b), 0, (int)nbytes, kRsrcWord3);
+}
+
+template <typename T, int AUX = 0>
+__device__ __forceinline__ T bload(Rsrc r, uint32_t off)
+{
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+}
+
+template <typename T, int AUX = 0>
+__device__ __forceinline__ void bstore(T v, Rsrc r, uint32_t off)
+{
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, off, 0, AUX);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, AUX);
+}
+
+// Byte offset of plane z (0 <= z < nz) advanced by one plane with wrap-around.
+__device__ __forceinline__ int64_t next_plane(int64_t zb, int64_t plane_b, int64_t field_b)
+{
+    const int64_t n = zb + plane_b;
+    return n == field_b ? 0 : n;
+}
+
 template <typename T, int TX, int TY>
 struct FusedShared {
     static constexpr int PX = TX + 4, PY = TY + 4, PP = PX * PY;
@@ -373,7 +442,7 @@ struct FusedShared {
     T v[2][PP];
     T p[2][PP];
     T w[3][PP];
-    CoefAB<T> tab[8];
+    Coef4<T> tab[8];
     double red[kNumSums * (TX * TY / 64)];
 };
 
@@ -454,23 +523,22 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
     const int z0 = bz * I.zc;
     const int z1 = min(z0 + I.zc, nz);
     const int64_t plane = (int64_t)nx * ny;
+    const int64_t plane_b = plane * (int64_t)sizeof(T), field_b = plane_b * nz;  // fields
+    const int64_t plane_c = plane * 4, field_c = plane_c * nz;                   // codes
     const int eff = parity ^ I.par_off;
-    // Pointers read from the instance table are generic; placing them in the
-    // global address space gives global (not flat) memory instructions, which
-    // do not share a wait counter with LDS traffic.
-    const T GLOBAL_AS *__restrict__ Uin = (const T GLOBAL_AS *)I.vel[eff][0];
-    const T GLOBAL_AS *__restrict__ Vin = (const T GLOBAL_AS *)I.vel[eff][1];
-    const T GLOBAL_AS *__restrict__ Win = (const T GLOBAL_AS *)I.vel[eff][2];
-    const T GLOBAL_AS *__restrict__ Pin = (const T GLOBAL_AS *)I.pres[eff];
-    T GLOBAL_AS *__restrict__ Uout = (T GLOBAL_AS *)I.vel[eff ^ 1][0];
-    T GLOBAL_AS *__restrict__ Vout = (T GLOBAL_AS *)I.vel[eff ^ 1][1];
-    T GLOBAL_AS *__restrict__ Wout = (T GLOBAL_AS *)I.vel[eff ^ 1][2];
-    T GLOBAL_AS *__restrict__ Pout = (T GLOBAL_AS *)I.pres[eff ^ 1];
-    const uint32_t GLOBAL_AS *__restrict__ codes = (const uint32_t GLOBAL_AS *)I.codes;
-    const T GLOBAL_AS *__restrict__ Su = (const T GLOBAL_AS *)I.src[0];
-    const T GLOBAL_AS *__restrict__ Sv = (const T GLOBAL_AS *)I.src[1];
-    const T GLOBAL_AS *__restrict__ Sw = (const T GLOBAL_AS *)I.src[2];
-    const T GLOBAL_AS *__restrict__ Sp = (const T GLOBAL_AS *)I.src[3];
+    const T *const Uin = (const T *)I.vel[eff][0];
+    const T *const Vin = (const T *)I.vel[eff][1];
+    const T *const Win = (const T *)I.vel[eff][2];
+    const T *const Pin = (const T *)I.pres[eff];
+    T *const Uout = (T *)I.vel[eff ^ 1][0];
+    T *const Vout = (T *)I.vel[eff ^ 1][1];
+    T *const Wout = (T *)I.vel[eff ^ 1][2];
+    T *const Pout = (T *)I.pres[eff ^ 1];
+    const uint32_t *const codes = I.codes;
+    const T *const Su = (const T *)I.src[0];
+    const T *const Sv = (const T *)I.src[1];
+    const T *const Sw = (const T *)I.src[2];
+    const T *const Sp = (const T *)I.src[3];
     const T nu = (T)I.nu, dt = (T)I.dt, c2dt = (T)I.c2dt;
     const T gu = I.axis == 0 ? (T)I.drive : T(0);
     const T gv = I.axis == 1 ? (T)I.drive : T(0);
@@ -479,20 +547,19 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    if (tid < 8) {
-        const Coef<T> c8 = coef_of_code<T>(tid);
-        sh.tab[tid] = {c8.a, c8.b};
-    }
+    fill_coef4(sh.tab, tid);
 
     // ---- own column (inactive threads hold the wrapped column: LDS stays periodic)
     const int gx = x0 + tx, gy = y0 + ty;
     const bool active = gx < nx && gy < ny;
     const int own = wrap_int(gy, ny) * nx + wrap_int(gx, nx);
+    const uint32_t own_b = (uint32_t)own * (uint32_t)sizeof(T), own_c = (uint32_t)own * 4u;
     const int cl = (ty + 2) * PX + (tx + 2);  // own position in the padded plane
 
     // ---- halo position of this thread in the padded plane (ring of width 2)
     const bool has_halo = tid < NHALO;
-    int hoff = 0, hlds = 0;
+    int hlds = 0;
+    uint32_t hoff_b = 0;
     bool has_ph = false;  // the -x column / -y row that p^{n-1} needs
     if (has_halo) {
         int px, py;
@@ -510,7 +577,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
             px = c < 2 ? c : PX - 4 + c;
         }
         hlds = py * PX + px;
-        hoff = wrap_int(y0 - 2 + py, ny) * nx + wrap_int(x0 - 2 + px, nx);
+        hoff_b = (uint32_t)(wrap_int(y0 - 2 + py, ny) * nx + wrap_int(x0 - 2 + px, nx)) * (uint32_t)sizeof(T);
         has_ph = (px == 1 && py >= 2 && py <= TY + 1) || (py == 1 && px >= 2 && px <= TX + 1);
     }
 
@@ -518,25 +585,28 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
     T Uw[5], Vw[5], Ww[3];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
-        const int64_t zo = (int64_t)wrap_int(z0 - 3 + j, nz) * plane + own;
-        Uw[j] = Uin[zo];
-        Vw[j] = Vin[zo];
+        const int64_t zb = (int64_t)wrap_int(z0 - 3 + j, nz) * plane_b;
+        Uw[j] = bload<T>(rsrc_at(Uin, zb, plane_b), own_b);
+        Vw[j] = bload<T>(rsrc_at(Vin, zb, plane_b), own_b);
     }
 #pragma unroll
-    for (int j = 0; j < 3; ++j) Ww[j] = Win[(int64_t)wrap_int(z0 - 2 + j, nz) * plane + own];
-    int zcur = wrap_int(z0 - 1, nz);  // zz
-    int z1p = wrap_int(z0, nz);       // zz + 1
-    int z2p = wrap_int(z0 + 1, nz);   // zz + 2
-    int z3p = wrap_int(z0 + 2, nz);   // zz + 3
-    T pold = Pin[(int64_t)zcur * plane + own];
+    for (int j = 0; j < 3; ++j)
+        Ww[j] = bload<T>(rsrc_at(Win, (int64_t)wrap_int(z0 - 2 + j, nz) * plane_b, plane_b), own_b);
+    // byte offsets of planes zz .. zz + 3 (fields) and zz + 1 (codes)
+    int64_t zb0 = (int64_t)wrap_int(z0 - 1, nz) * plane_b;
+    int64_t zb1 = next_plane(zb0, plane_b, field_b);
+    int64_t zb2 = next_plane(zb1, plane_b, field_b);
+    int64_t zb3 = next_plane(zb2, plane_b, field_b);
+    int64_t zc1 = (int64_t)wrap_int(z0, nz) * plane_c;
+    T pold = bload<T>(rsrc_at(Pin, zb0, plane_b), own_b);
     uint32_t code = 0;
     T sU = T(0), sV = T(0), sW = T(0), sP = T(0);  // correction-form terms of plane zz
     T hU = T(0), hV = T(0), hW = T(0), hP = T(0);
     if (has_halo) {
-        hU = Uin[(int64_t)zcur * plane + hoff];
-        hV = Vin[(int64_t)zcur * plane + hoff];
-        hW = Win[(int64_t)z1p * plane + hoff];
-        if (has_ph) hP = Pin[(int64_t)zcur * plane + hoff];
+        hU = bload<T>(rsrc_at(Uin, zb0, plane_b), hoff_b);
+        hV = bload<T>(rsrc_at(Vin, zb0, plane_b), hoff_b);
+        hW = bload<T>(rsrc_at(Win, zb1, plane_b), hoff_b);
+        if (has_ph) hP = bload<T>(rsrc_at(Pin, zb0, plane_b), hoff_b);
     }
     int slot = 0;                   // u, v, p slot of plane zz
     int wc = 0, wn = 1;             // w slots of planes zz and zz + 1
@@ -576,26 +646,27 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
         T bU = T(0), bV = T(0), bW = T(0), bP = T(0);
         T bSu = T(0), bSv = T(0), bSw = T(0), bSp = T(0);
         uint32_t bC = 0;
+        const Rsrc rU1 = rsrc_at(Uin, zb1, plane_b), rV1 = rsrc_at(Vin, zb1, plane_b);
+        const Rsrc rW2 = rsrc_at(Win, zb2, plane_b), rP1 = rsrc_at(Pin, zb1, plane_b);
         if (ahead) {
             if constexpr (SRC) {
-                const int64_t oa = (int64_t)z1p * plane + own;
-                bSu = __builtin_nontemporal_load(&Su[oa]);
-                bSv = __builtin_nontemporal_load(&Sv[oa]);
-                bSw = __builtin_nontemporal_load(&Sw[oa]);
-                bSp = __builtin_nontemporal_load(&Sp[oa]);
+                bSu = bload<T, kNonTemporal>(rsrc_at(Su, zb1, plane_b), own_b);
+                bSv = bload<T, kNonTemporal>(rsrc_at(Sv, zb1, plane_b), own_b);
+                bSw = bload<T, kNonTemporal>(rsrc_at(Sw, zb1, plane_b), own_b);
+                bSp = bload<T, kNonTemporal>(rsrc_at(Sp, zb1, plane_b), own_b);
             }
-            bU = Uin[(int64_t)z3p * plane + own];
-            bV = Vin[(int64_t)z3p * plane + own];
-            bW = Win[(int64_t)z2p * plane + own];
-            bP = Pin[(int64_t)z1p * plane + own];
-            bC = __builtin_nontemporal_load(&codes[(int64_t)z1p * plane + own]);
+            bU = bload<T>(rsrc_at(Uin, zb3, plane_b), own_b);
+            bV = bload<T>(rsrc_at(Vin, zb3, plane_b), own_b);
+            bW = bload<T>(rW2, own_b);
+            bP = bload<T>(rP1, own_b);
+            bC = bload<uint32_t, kNonTemporal>(rsrc_at(codes, zc1, plane_c), own_c);
         }
         T bhU = T(0), bhV = T(0), bhW = T(0), bhP = T(0);
         if (has_halo && ahead) {
-            bhU = Uin[(int64_t)z1p * plane + hoff];
-            bhV = Vin[(int64_t)z1p * plane + hoff];
-            bhW = Win[(int64_t)z2p * plane + hoff];
-            if (has_ph) bhP = Pin[(int64_t)z1p * plane + hoff];
+            bhU = bload<T>(rU1, hoff_b);
+            bhV = bload<T>(rV1, hoff_b);
+            bhW = bload<T>(rW2, hoff_b);
+            if (has_ph) bhP = bload<T>(rP1, hoff_b);
         }
         __syncthreads();
 
@@ -611,39 +682,38 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
             const T pxm = skip ? sp[cl - 1] : fma(-c2dt, dxm, sp[cl - 1]);
             const T dym = divergence(su[cl - PX], su[cl - PX + 1], sv[cl - PX], Vw[2], swc[cl - PX], swn[cl - PX]);
             const T pym = skip ? sp[cl - PX] : fma(-c2dt, dym, sp[cl - PX]);
-            const int64_t o = (int64_t)zcur * plane + own;
-            __builtin_nontemporal_store(SRC ? pn + sP : pn, &Pout[o]);
+            bstore<T, kNonTemporal>(SRC ? pn + sP : pn, rsrc_at(Pout, zb0, plane_b), own_b);
             // u: own axis x, across y (LDS) and z (registers)
             const uint32_t cu = code;
             const T u0 = Uw[2];
             const T u_d2x = d2_own(su[cl - 1], u0, su[cl + 1]);
-            const T u_d2y = d2_perp_tab(sh.tab, cu & 7, su[cl - 2 * PX], su[cl - PX], u0, su[cl + PX], su[cl + 2 * PX]);
-            const T u_d2z = d2_perp_tab(sh.tab, (cu >> 3) & 7, Uw[0], Uw[1], u0, Uw[3], Uw[4]);
+            const T u_d2y = d2_perp_t4(sh.tab, cu & 7, su[cl - 2 * PX], su[cl - PX], u0, su[cl + PX], su[cl + 2 * PX]);
+            const T u_d2z = d2_perp_t4(sh.tab, (cu >> 3) & 7, Uw[0], Uw[1], u0, Uw[3], Uw[4]);
             const T Fu = momentum(u_d2x, u_d2y, u_d2z, pn, pxm, nu, gu);
             const bool su_ = (cu & kSolidBit) != 0;
-            __builtin_nontemporal_store(su_ ? T(0) : (SRC ? fma(dt, Fu, u0) + sU : fma(dt, Fu, u0)),
-                                        &Uout[o]);
+            bstore<T, kNonTemporal>(su_ ? T(0) : (SRC ? fma(dt, Fu, u0) + sU : fma(dt, Fu, u0)),
+                                    rsrc_at(Uout, zb0, plane_b), own_b);
             // v: own axis y, across x (LDS) and z (registers)
             const uint32_t cv = code >> kCodeBits;
             const T v0 = Vw[2];
-            const T v_d2x = d2_perp_tab(sh.tab, cv & 7, sv[cl - 2], sv[cl - 1], v0, sv[cl + 1], sv[cl + 2]);
+            const T v_d2x = d2_perp_t4(sh.tab, cv & 7, sv[cl - 2], sv[cl - 1], v0, sv[cl + 1], sv[cl + 2]);
             const T v_d2y = d2_own(sv[cl - PX], v0, sv[cl + PX]);
-            const T v_d2z = d2_perp_tab(sh.tab, (cv >> 3) & 7, Vw[0], Vw[1], v0, Vw[3], Vw[4]);
+            const T v_d2z = d2_perp_t4(sh.tab, (cv >> 3) & 7, Vw[0], Vw[1], v0, Vw[3], Vw[4]);
             const T Fv = momentum(v_d2x, v_d2y, v_d2z, pn, pym, nu, gv);
             const bool sv_ = (cv & kSolidBit) != 0;
-            __builtin_nontemporal_store(sv_ ? T(0) : (SRC ? fma(dt, Fv, v0) + sV : fma(dt, Fv, v0)),
-                                        &Vout[o]);
+            bstore<T, kNonTemporal>(sv_ ? T(0) : (SRC ? fma(dt, Fv, v0) + sV : fma(dt, Fv, v0)),
+                                    rsrc_at(Vout, zb0, plane_b), own_b);
             // w: own axis z (registers), across x and y (LDS)
             const uint32_t cw = code >> (2 * kCodeBits);
             const T w0 = Ww[1];
-            const T w_d2x = d2_perp_tab(sh.tab, cw & 7, swc[cl - 2], swc[cl - 1], w0, swc[cl + 1], swc[cl + 2]);
-            const T w_d2y = d2_perp_tab(sh.tab, (cw >> 3) & 7, swc[cl - 2 * PX], swc[cl - PX], w0, swc[cl + PX],
-                                    swc[cl + 2 * PX]);
+            const T w_d2x = d2_perp_t4(sh.tab, cw & 7, swc[cl - 2], swc[cl - 1], w0, swc[cl + 1], swc[cl + 2]);
+            const T w_d2y = d2_perp_t4(sh.tab, (cw >> 3) & 7, swc[cl - 2 * PX], swc[cl - PX], w0, swc[cl + PX],
+                                       swc[cl + 2 * PX]);
             const T w_d2z = d2_own(Ww[0], w0, Ww[2]);
             const T Fw = momentum(w_d2x, w_d2y, w_d2z, pn, pn_prev, nu, gw);
             const bool sw_ = (cw & kSolidBit) != 0;
-            __builtin_nontemporal_store(sw_ ? T(0) : (SRC ? fma(dt, Fw, w0) + sW : fma(dt, Fw, w0)),
-                                        &Wout[o]);
+            bstore<T, kNonTemporal>(sw_ ? T(0) : (SRC ? fma(dt, Fw, w0) + sW : fma(dt, Fw, w0)),
+                                    rsrc_at(Wout, zb0, plane_b), own_b);
             if (RED && !SRC && active) {
                 const double fu = su_ ? 0.0 : (double)Fu, fv = sv_ ? 0.0 : (double)Fv,
                              fw = sw_ ? 0.0 : (double)Fw;
@@ -688,10 +758,11 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
         hV = bhV;
         hW = bhW;
         hP = bhP;
-        zcur = z1p;
-        z1p = z2p;
-        z2p = z3p;
-        z3p = (z3p + 1 == nz) ? 0 : z3p + 1;
+        zb0 = zb1;
+        zb1 = zb2;
+        zb2 = zb3;
+        zb3 = next_plane(zb3, plane_b, field_b);
+        zc1 = next_plane(zc1, plane_c, field_c);
         slot ^= 1;
         wc = wn;
         wn = (wn == 2) ? 0 : wn + 1;
@@ -702,6 +773,423 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) expcnt(7) lgkmcnt(15)
     for (int zz = z0; zz < z1; ++zz) plane_step(zz, BoolC<true>{});
     if (RED) block_sums(acc, sh.red, I.partials + lb * kNumSums);
+}
+
+// ============================================================== two sweeps per pass
+//
+// The same fused step applied twice per HBM pass (temporal blocking, T = 2):
+//
+//   stage 1  (v^n, p^{n-1})     -> p^n, v^{n+1}   over the workgroup's region
+//   stage 2  (v^{n+1}, p^n)     -> p^{n+1}, v^{n+2}  over the region's interior
+//
+// The stencil of one fused step reaches two cells across the flow (App. B), so
+// an output tile of OX x OY columns needs stage 1 on the tile plus a ring of two
+// columns: the workgroup holds one thread per column of that (OX + 4) x (OY + 4)
+// region, and its stage-1 inputs come with a further ring of two (as in the
+// single-step kernel).  Along z, stage 2 trails stage 1 by two planes; the stage-1
+// results of a thread's own column stay in register windows (5 planes of u and v,
+// 4 of w, 3 of p^n), and the plane stage 2 works on is staged in LDS for the
+// neighbours.  Only v^n, p^{n-1} and the codes are read from HBM and only
+// v^{n+2}, p^{n+1} written: the bytes of one sweep for two.  Ring threads compute
+// stage 1 only; each output tile repeats the stage-1 work of its ring, and each
+// z-chunk the stage-1 work of four planes beyond its ends.
+//
+// Every value is computed by the same expressions, in the same order, as in the
+// single-step kernel (the drive, the App. B table, fma placement), so two stages
+// here are bitwise two launches there.  Launches of this kernel never carry the
+// reduction and never skip the pressure update: the first step of a pipeline and
+// the step at a convergence check run as single steps.
+
+template <typename T, int OX, int OY>
+struct Fused2Shared {
+    static constexpr int SX = OX + 4, SY = OY + 4, NT = SX * SY;  // stage-1 region: one thread per column
+    static constexpr int PX = SX + 4, PY = SY + 4, PP = PX * PY;  // stage-1 inputs: the region plus a ring of 2
+    T u[PP];
+    T v[PP];
+    T p[PP];
+    T w[2][PP];
+    T u2[NT];  // stage-1 results of the plane stage 2 works on
+    T v2[NT];
+    T p2[NT];
+    T w2[2][NT];
+    Coef4<T> tab[8];
+};
+
+template <typename T, int OX, int OY>
+__global__ void __launch_bounds__((OX + 4) * (OY + 4))
+k_fused2(const InstDev *__restrict__ insts, int ninst, int parity)
+{
+    using SH = Fused2Shared<T, OX, OY>;
+    constexpr int SX = SH::SX, SY = SH::SY, NT = SH::NT, PX = SH::PX, PY = SH::PY;
+    constexpr int NHALO = PX * PY - NT;
+    static_assert(NHALO <= NT, "one halo position per thread");
+    __shared__ SH sh;
+
+    // ---- XCD-aware order: a contiguous run of tiles per XCD (its own L2), the
+    // runs rotated when a plane holds 256 or more tiles (as the FP32 single-step
+    // kernel); blocks are only permuted
+    const int64_t nbk = gridDim.x, xcd = blockIdx.x % kNumXcd, kx = blockIdx.x / kNumXcd;
+    int64_t b;
+    {
+        const int64_t q = nbk / kNumXcd, rem = nbk % kNumXcd;
+        const int64_t qx = xcd < rem ? q + 1 : q;
+        const bool rotate = (int64_t)insts[0].tiles_x * insts[0].tiles_y >= 256;
+        b = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) +
+            (rotate ? (kx + xcd * (qx / kNumXcd)) % qx : kx);
+    }
+
+    // ---- instance of this block (ranges are sorted by blk_begin)
+    int lo = 0, hi = ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (insts[mid].blk_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const InstDev &I = insts[lo];
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
+    const int64_t lb = b - I.blk_begin;
+    const int bx = (int)(lb % I.tiles_x);
+    const int64_t rr = lb / I.tiles_x;
+    const int by = (int)(rr % I.tiles_y);
+    const int bz = (int)(rr / I.tiles_y);
+    const int X1 = bx * OX - 2, Y1 = by * OY - 2;  // origin of the stage-1 region
+    const int z0 = bz * I.zc;
+    const int zend = min(z0 + I.zc, nz);
+    const int64_t plane = (int64_t)nx * ny;
+    const int64_t plane_b = plane * (int64_t)sizeof(T), field_b = plane_b * nz;
+    const int64_t plane_c = plane * 4, field_c = plane_c * nz;
+    const int eff = parity ^ I.par_off;
+    const T *const Uin = (const T *)I.vel[eff][0];
+    const T *const Vin = (const T *)I.vel[eff][1];
+    const T *const Win = (const T *)I.vel[eff][2];
+    const T *const Pin = (const T *)I.pres[eff];
+    T *const Uout = (T *)I.vel[eff ^ 1][0];
+    T *const Vout = (T *)I.vel[eff ^ 1][1];
+    T *const Wout = (T *)I.vel[eff ^ 1][2];
+    T *const Pout = (T *)I.pres[eff ^ 1];
+    const uint32_t *const codes = I.codes;
+    const T nu = (T)I.nu, dt = (T)I.dt, c2dt = (T)I.c2dt;
+    const T gu = I.axis == 0 ? (T)I.drive : T(0);
+    const T gv = I.axis == 1 ? (T)I.drive : T(0);
+    const T gw = I.axis == 2 ? (T)I.drive : T(0);
+
+    const int tid = threadIdx.x;
+    const int tx = tid % SX, ty = tid / SX;
+    fill_coef4(sh.tab, tid);
+
+    // ---- own column (wrapped: the region may reach across the periodic boundary)
+    const bool is_out = tx >= 2 && tx < SX - 2 && ty >= 2 && ty < SY - 2;
+    const int own = wrap_int(Y1 + ty, ny) * nx + wrap_int(X1 + tx, nx);
+    const uint32_t own_b = (uint32_t)own * (uint32_t)sizeof(T), own_c = (uint32_t)own * 4u;
+    // stores: output lanes at their column (lanes of a column beyond the grid
+    // store the identical values of the wrapped column); ring lanes beyond the
+    // plane, where the store is dropped, so that every step stores
+    // unconditionally (a path without the stores made the compiler wait for
+    // each step's stores before the next loads, see the single-step kernel)
+    const uint32_t st_b = is_out ? own_b : kOffNone;
+    const int cl = (ty + 2) * PX + (tx + 2);  // stage-1 position in the padded plane
+    const int c2 = tid;                       // stage-2 position (ty * SX + tx)
+
+    // ---- halo position of this thread in the padded stage-1 plane (ring of width 2)
+    const bool has_halo = tid < NHALO;
+    int hlds = 0;
+    uint32_t hoff_b = 0;
+    bool has_ph = false;  // the -x column / -y row that p^{n-1} needs
+    if (has_halo) {
+        int px, py;
+        if (tid < 2 * PX) {
+            py = tid / PX;
+            px = tid % PX;
+        } else if (tid < 4 * PX) {
+            const int hh = tid - 2 * PX;
+            py = PY - 2 + hh / PX;
+            px = hh % PX;
+        } else {
+            const int hh = tid - 4 * PX;
+            py = 2 + hh / 4;
+            const int c = hh % 4;
+            px = c < 2 ? c : PX - 4 + c;
+        }
+        hlds = py * PX + px;
+        hoff_b = (uint32_t)(wrap_int(Y1 - 2 + py, ny) * nx + wrap_int(X1 - 2 + px, nx)) * (uint32_t)sizeof(T);
+        has_ph = (px == 1 && py >= 2 && py <= SY + 1) || (py == 1 && px >= 2 && px <= SX + 1);
+    }
+
+    // ---- stage-1 windows, primed for the prologue plane zz = z0 - 3
+    T Uw[5], Vw[5], Ww[3];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const int64_t zb = (int64_t)wrap_int(z0 - 5 + j, nz) * plane_b;
+        Uw[j] = bload<T>(rsrc_at(Uin, zb, plane_b), own_b);
+        Vw[j] = bload<T>(rsrc_at(Vin, zb, plane_b), own_b);
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        Ww[j] = bload<T>(rsrc_at(Win, (int64_t)wrap_int(z0 - 4 + j, nz) * plane_b, plane_b), own_b);
+    int64_t zb0 = (int64_t)wrap_int(z0 - 3, nz) * plane_b;  // zz
+    int64_t zb1 = next_plane(zb0, plane_b, field_b);         // zz + 1
+    int64_t zb2 = next_plane(zb1, plane_b, field_b);         // zz + 2
+    int64_t zb3 = next_plane(zb2, plane_b, field_b);         // zz + 3
+    int64_t zc1 = (int64_t)wrap_int(z0 - 2, nz) * plane_c;  // codes of zz + 1
+    int64_t zout = (int64_t)wrap_int(z0 - 1, nz) * plane_b;  // the plane of the next stage-2 step
+    T pold = bload<T>(rsrc_at(Pin, zb0, plane_b), own_b);
+    uint32_t code = 0;
+    T hU = T(0), hV = T(0), hW = T(0), hP = T(0);
+    if (has_halo) {
+        hU = bload<T>(rsrc_at(Uin, zb0, plane_b), hoff_b);
+        hV = bload<T>(rsrc_at(Vin, zb0, plane_b), hoff_b);
+        hW = bload<T>(rsrc_at(Win, zb1, plane_b), hoff_b);
+        if (has_ph) hP = bload<T>(rsrc_at(Pin, zb0, plane_b), hoff_b);
+    }
+    int wc = 0, wn = 1;    // stage-1 w slots of planes zz and zz + 1
+    int wc2 = 0, wn2 = 1;  // stage-2 w slots of planes z2 and z2 + 1
+    T pn_prev = T(0), pn_prev2 = T(0);
+    // stage-1 results of the own column: u, v at zz-4..zz, w at zz-3..zz, p^n at
+    // zz-2..zz, codes at zz-2..zz
+    T U1[5], V1[5], W1[4], P1[3];
+    uint32_t C1[3] = {0u, 0u, 0u};
+#pragma unroll
+    for (int j = 0; j < 5; ++j) U1[j] = V1[j] = T(0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) W1[j] = T(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) P1[j] = T(0);
+
+    // One stage-1 step on plane zz (body: the velocity update too); the
+    // prologue plane only primes p^n.  stage1_only: no stage-2 step follows,
+    // whose barrier would otherwise separate this step's LDS reads from the
+    // next step's staging.
+    auto stage1 = [&](const int zz, auto body_c, auto only_c) __attribute__((always_inline)) {
+        constexpr bool body = decltype(body_c)::value;
+        constexpr bool stage1_only = decltype(only_c)::value;
+        T *const su = sh.u;
+        T *const sv = sh.v;
+        T *const sp = sh.p;
+        T *const swc = sh.w[wc];
+        T *const swn = sh.w[wn];
+        su[cl] = Uw[2];
+        sv[cl] = Vw[2];
+        sp[cl] = pold;
+        swn[cl] = Ww[2];
+        if (has_halo) {
+            su[hlds] = hU;
+            sv[hlds] = hV;
+            swn[hlds] = hW;
+            if (has_ph) sp[hlds] = hP;
+        }
+        // loads for plane zz + 1 (stage 1 runs to zend + 1)
+        const bool ahead = zz + 1 <= zend + 1;
+        T bU = T(0), bV = T(0), bW = T(0), bP = T(0);
+        uint32_t bC = 0;
+        const Rsrc rU1 = rsrc_at(Uin, zb1, plane_b), rV1 = rsrc_at(Vin, zb1, plane_b);
+        const Rsrc rW2 = rsrc_at(Win, zb2, plane_b), rP1 = rsrc_at(Pin, zb1, plane_b);
+        if (ahead) {
+            bU = bload<T>(rsrc_at(Uin, zb3, plane_b), own_b);
+            bV = bload<T>(rsrc_at(Vin, zb3, plane_b), own_b);
+            bW = bload<T>(rW2, own_b);
+            bP = bload<T>(rP1, own_b);
+            bC = bload<uint32_t, kNonTemporal>(rsrc_at(codes, zc1, plane_c), own_c);
+        }
+        T bhU = T(0), bhV = T(0), bhW = T(0), bhP = T(0);
+        if (has_halo && ahead) {
+            bhU = bload<T>(rU1, hoff_b);
+            bhV = bload<T>(rV1, hoff_b);
+            bhW = bload<T>(rW2, hoff_b);
+            if (has_ph) bhP = bload<T>(rP1, hoff_b);
+        }
+        __syncthreads();
+
+        const T dvg = divergence(Uw[2], su[cl + 1], Vw[2], sv[cl + PX], Ww[1], Ww[2]);
+        const T pn = fma(-c2dt, dvg, pold);
+        if constexpr (body) {
+            const T dxm = divergence(su[cl - 1], Uw[2], sv[cl - 1], sv[cl - 1 + PX], swc[cl - 1], swn[cl - 1]);
+            const T pxm = fma(-c2dt, dxm, sp[cl - 1]);
+            const T dym = divergence(su[cl - PX], su[cl - PX + 1], sv[cl - PX], Vw[2], swc[cl - PX], swn[cl - PX]);
+            const T pym = fma(-c2dt, dym, sp[cl - PX]);
+            const uint32_t cu = code;
+            const T u0 = Uw[2];
+            const T u_d2x = d2_own(su[cl - 1], u0, su[cl + 1]);
+            const T u_d2y = d2_perp_t4(sh.tab, cu & 7, su[cl - 2 * PX], su[cl - PX], u0, su[cl + PX], su[cl + 2 * PX]);
+            const T u_d2z = d2_perp_t4(sh.tab, (cu >> 3) & 7, Uw[0], Uw[1], u0, Uw[3], Uw[4]);
+            const T Fu = momentum(u_d2x, u_d2y, u_d2z, pn, pxm, nu, gu);
+            const T u1 = (cu & kSolidBit) != 0 ? T(0) : fma(dt, Fu, u0);
+            const uint32_t cv = code >> kCodeBits;
+            const T v0 = Vw[2];
+            const T v_d2x = d2_perp_t4(sh.tab, cv & 7, sv[cl - 2], sv[cl - 1], v0, sv[cl + 1], sv[cl + 2]);
+            const T v_d2y = d2_own(sv[cl - PX], v0, sv[cl + PX]);
+            const T v_d2z = d2_perp_t4(sh.tab, (cv >> 3) & 7, Vw[0], Vw[1], v0, Vw[3], Vw[4]);
+            const T Fv = momentum(v_d2x, v_d2y, v_d2z, pn, pym, nu, gv);
+            const T v1 = (cv & kSolidBit) != 0 ? T(0) : fma(dt, Fv, v0);
+            const uint32_t cw = code >> (2 * kCodeBits);
+            const T w0 = Ww[1];
+            const T w_d2x = d2_perp_t4(sh.tab, cw & 7, swc[cl - 2], swc[cl - 1], w0, swc[cl + 1], swc[cl + 2]);
+            const T w_d2y = d2_perp_t4(sh.tab, (cw >> 3) & 7, swc[cl - 2 * PX], swc[cl - PX], w0, swc[cl + PX],
+                                       swc[cl + 2 * PX]);
+            const T w_d2z = d2_own(Ww[0], w0, Ww[2]);
+            const T Fw = momentum(w_d2x, w_d2y, w_d2z, pn, pn_prev, nu, gw);
+            const T w1 = (cw & kSolidBit) != 0 ? T(0) : fma(dt, Fw, w0);
+            // push the results of plane zz into the own-column windows
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                U1[j] = U1[j + 1];
+                V1[j] = V1[j + 1];
+            }
+            U1[4] = u1;
+            V1[4] = v1;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) W1[j] = W1[j + 1];
+            W1[3] = w1;
+            P1[0] = P1[1];
+            P1[1] = P1[2];
+            P1[2] = pn;
+            C1[0] = C1[1];
+            C1[1] = C1[2];
+            C1[2] = code;
+        }
+        if constexpr (stage1_only) __syncthreads();
+
+        // ---- advance
+        pn_prev = pn;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            Uw[j] = Uw[j + 1];
+            Vw[j] = Vw[j + 1];
+        }
+        Uw[4] = bU;
+        Vw[4] = bV;
+        Ww[0] = Ww[1];
+        Ww[1] = Ww[2];
+        Ww[2] = bW;
+        pold = bP;
+        code = bC;
+        hU = bhU;
+        hV = bhV;
+        hW = bhW;
+        hP = bhP;
+        zb0 = zb1;
+        zb1 = zb2;
+        zb2 = zb3;
+        zb3 = next_plane(zb3, plane_b, field_b);
+        zc1 = next_plane(zc1, plane_c, field_c);
+        wc = wn;
+        wn ^= 1;
+    };
+
+    // One stage-2 step on the plane two below the last stage-1 plane (body:
+    // the velocity update and the stores; the prologue plane primes p^{n+1}).
+    auto stage2 = [&](auto body_c) __attribute__((always_inline)) {
+        constexpr bool body = decltype(body_c)::value;
+        T *const su = sh.u2;
+        T *const sv = sh.v2;
+        T *const sp = sh.p2;
+        T *const swc = sh.w2[wc2];
+        T *const swn = sh.w2[wn2];
+        su[c2] = U1[2];
+        sv[c2] = V1[2];
+        sp[c2] = P1[0];
+        swn[c2] = W1[2];
+        __syncthreads();
+        T pn = T(0);
+        if (is_out) {
+            const T dvg = divergence(U1[2], su[c2 + 1], V1[2], sv[c2 + SX], W1[1], W1[2]);
+            pn = fma(-c2dt, dvg, P1[0]);
+        }
+        if constexpr (body) {
+            T ru = T(0), rv = T(0), rw = T(0);
+            if (is_out) {
+                const T dxm = divergence(su[c2 - 1], U1[2], sv[c2 - 1], sv[c2 - 1 + SX], swc[c2 - 1], swn[c2 - 1]);
+                const T pxm = fma(-c2dt, dxm, sp[c2 - 1]);
+                const T dym =
+                    divergence(su[c2 - SX], su[c2 - SX + 1], sv[c2 - SX], V1[2], swc[c2 - SX], swn[c2 - SX]);
+                const T pym = fma(-c2dt, dym, sp[c2 - SX]);
+                const uint32_t cu = C1[0];
+                const T u0 = U1[2];
+                const T u_d2x = d2_own(su[c2 - 1], u0, su[c2 + 1]);
+                const T u_d2y =
+                    d2_perp_t4(sh.tab, cu & 7, su[c2 - 2 * SX], su[c2 - SX], u0, su[c2 + SX], su[c2 + 2 * SX]);
+                const T u_d2z = d2_perp_t4(sh.tab, (cu >> 3) & 7, U1[0], U1[1], u0, U1[3], U1[4]);
+                const T Fu = momentum(u_d2x, u_d2y, u_d2z, pn, pxm, nu, gu);
+                ru = (cu & kSolidBit) != 0 ? T(0) : fma(dt, Fu, u0);
+                const uint32_t cv = cu >> kCodeBits;
+                const T v0 = V1[2];
+                const T v_d2x = d2_perp_t4(sh.tab, cv & 7, sv[c2 - 2], sv[c2 - 1], v0, sv[c2 + 1], sv[c2 + 2]);
+                const T v_d2y = d2_own(sv[c2 - SX], v0, sv[c2 + SX]);
+                const T v_d2z = d2_perp_t4(sh.tab, (cv >> 3) & 7, V1[0], V1[1], v0, V1[3], V1[4]);
+                const T Fv = momentum(v_d2x, v_d2y, v_d2z, pn, pym, nu, gv);
+                rv = (cv & kSolidBit) != 0 ? T(0) : fma(dt, Fv, v0);
+                const uint32_t cw = cu >> (2 * kCodeBits);
+                const T w0 = W1[1];
+                const T w_d2x = d2_perp_t4(sh.tab, cw & 7, swc[c2 - 2], swc[c2 - 1], w0, swc[c2 + 1], swc[c2 + 2]);
+                const T w_d2y = d2_perp_t4(sh.tab, (cw >> 3) & 7, swc[c2 - 2 * SX], swc[c2 - SX], w0, swc[c2 + SX],
+                                           swc[c2 + 2 * SX]);
+                const T w_d2z = d2_own(W1[0], w0, W1[2]);
+                const T Fw = momentum(w_d2x, w_d2y, w_d2z, pn, pn_prev2, nu, gw);
+                rw = (cw & kSolidBit) != 0 ? T(0) : fma(dt, Fw, w0);
+            }
+            bstore<T, kNonTemporal>(pn, rsrc_at(Pout, zout, plane_b), st_b);
+            bstore<T, kNonTemporal>(ru, rsrc_at(Uout, zout, plane_b), st_b);
+            bstore<T, kNonTemporal>(rv, rsrc_at(Vout, zout, plane_b), st_b);
+            bstore<T, kNonTemporal>(rw, rsrc_at(Wout, zout, plane_b), st_b);
+        }
+        pn_prev2 = pn;
+        zout = next_plane(zout, plane_b, field_b);
+        wc2 = wn2;
+        wn2 ^= 1;
+    };
+
+    // stage 1 on planes z0 - 3 (prologue) .. zend + 1; stage 2 two planes behind,
+    // on z0 - 1 (prologue) .. zend - 1
+    stage1(z0 - 3, BoolC<false>{}, BoolC<true>{});
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the prologue's loads are in the carried registers
+    stage1(z0 - 2, BoolC<true>{}, BoolC<true>{});
+    stage1(z0 - 1, BoolC<true>{}, BoolC<true>{});
+    stage1(z0, BoolC<true>{}, BoolC<true>{});
+    stage1(z0 + 1, BoolC<true>{}, BoolC<false>{});
+    stage2(BoolC<false>{});
+    // no stores since the last loads: complete them here, or the loop head would
+    // wait for the stores of every step as well
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    for (int zz = z0 + 2; zz <= zend + 1; ++zz) {
+        stage1(zz, BoolC<true>{}, BoolC<false>{});
+        stage2(BoolC<true>{});
+    }
+}
+
+bool fused2_tile_supported(int ox, int oy, int prec)
+{
+    (void)prec;
+    return (ox == 64 && oy == 10) || (ox == 64 && oy == 8) || (ox == 64 && oy == 6) || (ox == 32 && oy == 24) ||
+           (ox == 32 && oy == 12) || (ox == 32 && oy == 8);
+}
+
+template <typename T>
+static hipError_t launch_fused2_t(int ox, int oy, const InstDev *insts, int ninst, int64_t nblocks, int parity,
+                                  hipStream_t s)
+{
+    const dim3 grid((unsigned)nblocks);
+#define PS_FUSED2_CASE(OX_, OY_)                                                                            \
+    if (ox == OX_ && oy == OY_) {                                                                          \
+        hipLaunchKernelGGL((k_fused2<T, OX_, OY_>), grid, dim3((OX_ + 4) * (OY_ + 4)), 0, s, insts, ninst,    \
+                           parity);                                                                        \
+        return hipGetLastError();                                                                          \
+    }
+    PS_FUSED2_CASE(64, 10)
+    PS_FUSED2_CASE(64, 8)
+    PS_FUSED2_CASE(64, 6)
+    PS_FUSED2_CASE(32, 24)
+    PS_FUSED2_CASE(32, 12)
+    PS_FUSED2_CASE(32, 8)
+#undef PS_FUSED2_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fused2(Prec prec, int ox, int oy, const InstDev *insts, int ninst, int64_t nblocks, int parity,
+                         hipStream_t s)
+{
+    if (nblocks <= 0 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (!fused2_tile_supported(ox, oy, prec)) return hipErrorInvalidValue;
+    return prec == kF64 ? launch_fused2_t<double>(ox, oy, insts, ninst, nblocks, parity, s)
+                        : launch_fused2_t<float>(ox, oy, insts, ninst, nblocks, parity, s);
 }
 
 bool fused_alone(Prec prec, int tx, int ty, int64_t tiles_per_plane)

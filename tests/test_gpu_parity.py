@@ -382,8 +382,11 @@ def test_autotune_choice_is_supported_and_exact(prec):
         ref = c.solve(m, 0, ps.params(precision=prec, max_sweeps=300))
         best = c.autotune(m, prec)
         assert tuple(best[:2]) in {(128, 8), (64, 8), (64, 16), (32, 8), (32, 16)} and 1 <= best[2] <= 30
+        assert best[3] in (1, 2) and (best[4], best[5]) in {(64, 10), (64, 8), (64, 6), (32, 24), (32, 12), (32, 8)}
+        assert 1 <= best[6] <= 30
         tuned = c.solve(m, 0, ps.params(precision=prec, max_sweeps=300))
-        assert c.last_stats()["tile_x"] == best[0] and c.last_stats()["zchunk"] == best[2]
+        st = c.last_stats()
+        assert st["tile_x"] == best[0] and st["zchunk"] == best[2] and st["tblock"] == best[3]
         # the iterate is bitwise identical; sums over another block decomposition
         # differ by rounding of the summation order only
         for fa, fb in zip(ref.fields, tuned.fields):
@@ -504,6 +507,7 @@ def test_fp32_dc_correction_form_yields_to_the_cap():
     with ps.Context(0, mem_cap=peak + 4096) as c:
         got = c.solve(m, 0, ps.params(precision=ps.FP32_DC))
         assert c.last_stats()["precision"] == ps.FP64
+        assert c.last_stats()["dc_promoted_for_memory"] == 1
     assert got.status == want.status == "OK" and got.sweeps == want.sweeps
     assert np.array_equal(got.kcol, want.kcol)
 
@@ -524,8 +528,16 @@ def test_batch_clogged_instance_only_changes_its_status(ctx):
     probs = [(ps.to_device(open_), 0), (ps.to_device(clogged), 0), (ps.to_device(open_), 1)]
     st, res = ctx.solve_batch(probs, ps.params())
     assert [r["status"] for r in res][0] == "OK" and res[2]["status"] == "OK"
-    assert res[1]["status"] in ("OK", "NO_FLOW")
-    assert abs(res[1]["kcol"][0]) < 1e-6 * res[0]["kcol"][0]
+    assert res[1]["status"] == "OK"
+    # The solid plane x = 7 carries exactly zero flux, and by the slice-flux
+    # identity every x-slice flux differs from it by a sum of cell divergences:
+    # |Q_x(s)| <= sqrt(N) |d|_2 with |nu d|_2 <= r G sqrt(N_f) (definition of r).
+    # Averaged over the nx slices, k_x = q_x / (Re G) <= nx sqrt(N_f / N) r <= nx r,
+    # with r the residual of the reported state (< tol = 1e-8).
+    nx = clogged.shape[2]
+    r_last = res[1]["r"][-1]
+    assert r_last < 1e-8
+    assert abs(res[1]["kcol"][0]) <= nx * r_last * (1 + 1e-9)
     single = ctx.solve(probs[0][0], 0)
     assert np.array_equal(res[0]["kcol"], single.kcol)
 
@@ -540,3 +552,25 @@ def test_fp32_dc_stays_fp32_far_above_its_floor(ctx):
     assert r.status == "NOT_CONVERGED"
     assert r.hist_r[-1] > 1e-2
     assert ctx.last_stats()["precision"] == ps.FP32
+
+
+@pytest.mark.parametrize("prec", [ps.FP64, ps.FP32_DC])
+def test_tensor_runs_cases_one_after_another_when_they_do_not_fit(prec):
+    """Under a cap that holds one load case but not three, pm_tensor solves the
+    axes one after another: the same tensor, sweeps and histories as the batch."""
+    mask = synth.test_grid(100)
+    m = ps.to_device(mask)
+    prm = ps.params(precision=prec)
+    with ps.Context(0) as c:
+        want = c.tensor(m, prm)
+        assert c.last_stats()["tensor_cases_at_once"] == 3
+    with ps.Context(0, mem_cap=120 * mask.size) as c:
+        got = c.tensor(m, prm)
+        st = c.last_stats()
+        assert st["tensor_cases_at_once"] == 1
+        assert st["dc_promoted_for_memory"] == 0
+        assert st["sweep_launches"] > 0
+    assert got.status == want.status == "OK"
+    assert np.array_equal(got.k, want.k) and np.array_equal(got.sweeps, want.sweeps)
+    for a, b in zip(got.hists, want.hists):
+        assert np.array_equal(a["r"], b["r"])
