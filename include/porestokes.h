@@ -223,6 +223,26 @@ pm_status pm_iterate(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx,
                      void *p, int64_t count);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): pm_iterate
+ * without any allocation.  Same arguments, checks and results as pm_iterate
+ * (bitwise), for grids whose stencil codes (4 B per voxel) and second field
+ * set (4 values per voxel in the call's precision) fit, with a 1 KiB table,
+ * in PM_STATIC_SCRATCH_BYTES: up to about 1.86 M voxels in PM_FP64 (123^3) and
+ * 3.35 M in PM_FP32 (149^3).  Larger grids are rejected with PM_ERR_ARG before
+ * any device work.  The scratch is one static device array per GPU, held from
+ * the moment the library is loaded on that GPU until the process ends, and
+ * shared by every call on it: calls on one GPU whose sweeps overlap in time
+ * (different streams or threads) race on it and must be serialised by the
+ * caller.  Every byte a call reads from it, the call writes first.  The call
+ * returns once its sweeps are complete; pm_last_stats reports no timing for it.
+ */
+#define PM_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+pm_status pm_iterate_static(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny,
+                            int64_t nz, int axis, const pm_params *params, void *u, void *v, void *w,
+                            void *p, int64_t count);
+
+/*
  * Residual sums of a state, computed in FP64 on the GPU: out[0] = S_F (sum of
  * squared momentum residuals over fluid faces), out[1] = S_D (sum of squared
  * nu*div v over cells), out[2..4] = sums of u, v, w over all faces.  Fields as

@@ -30,7 +30,7 @@ KERNEL_AUTO, KERNEL_FUSED, KERNEL_SIMPLE = 0, 1, 2
 EXPORTS = ("pm_params_default", "pm_status_string", "pm_create", "pm_destroy", "pm_last_error",
            "pm_mem_used", "pm_preprocess", "pm_face_codes", "pm_iterate", "pm_residual", "pm_solve",
            "pm_tensor", "pm_solve_batch", "pm_last_stats", "pm_autotune", "pm_principal_axes",
-           "pm_plane_angle", "pm_pores", "pm_mirror", "pm_trim")
+           "pm_plane_angle", "pm_pores", "pm_mirror", "pm_trim", "pm_iterate_static")
 ISOTROPIC, TRANSVERSE, ORTHOTROPIC = 0, 1, 2
 CLASS_NAMES = {ISOTROPIC: "isotropic", TRANSVERSE: "transverse", ORTHOTROPIC: "orthotropic"}
 
@@ -174,6 +174,8 @@ def load_library(path: str = LIB_PATH):
     lib.pm_face_codes.restype = i32
     lib.pm_iterate.argtypes = [vp, vp, vp, i64, i64, i64, i32, pp, vp, vp, vp, vp, i64]
     lib.pm_iterate.restype = i32
+    lib.pm_iterate_static.argtypes = [vp, vp, vp, i64, i64, i64, i32, pp, vp, vp, vp, vp, i64]
+    lib.pm_iterate_static.restype = i32
     lib.pm_residual.argtypes = [vp, vp, vp, i64, i64, i64, i32, pp, vp, vp, vp, vp, vp]
     lib.pm_residual.restype = i32
     lib.pm_solve.argtypes = [vp, vp, vp, i64, i64, i64, ctypes.c_double, ctypes.c_double, i32, pp,
@@ -372,6 +374,15 @@ class Context:
         f = [_dev_tensor(t, None, "field") for t in fields]
         self._check(self._lib.pm_iterate(self._h, _stream(), m.data_ptr(), nx, ny, nz, axis,
                                          ctypes.byref(prm), *[t.data_ptr() for t in f], count))
+        return fields
+
+    def iterate_static(self, mask, axis: int, fields, count: int, prm: PmParams | None = None):
+        """pm_iterate_static: as iterate, on the library's static device scratch (no allocation)."""
+        m, nx, ny, nz = _mask3(mask)
+        prm = prm or params()
+        f = [_dev_tensor(t, None, "field") for t in fields]
+        self._check(self._lib.pm_iterate_static(self._h, _stream(), m.data_ptr(), nx, ny, nz, axis,
+                                                ctypes.byref(prm), *[t.data_ptr() for t in f], count))
         return fields
 
     def residual(self, mask, axis: int, fields, prm: PmParams | None = None) -> np.ndarray:

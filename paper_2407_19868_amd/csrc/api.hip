@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -1652,6 +1653,53 @@ pm_status check_iterate_args(pm_ctx *ctx, const uint8_t *mask, int64_t nx, int64
 
 }  // namespace
 
+// ------------------------------------------------------------ no allocation
+//
+// pm_iterate_static runs pm_iterate's sweeps on device memory that exists
+// from the moment the library's code object is loaded on a GPU: one array
+// per GPU, shared by every call on it.  Host code never uses the array's
+// name as a device address; pm_create looks the address up once per device.
+static __device__ __align__(256) unsigned char scratch[PM_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};
+
+// Address of this device's array (the device is current); once per device.
+pm_status static_scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return PM_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_ptr[dev]) return PM_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return PM_ERR_DEVICE;
+    }
+    g_static_ptr[dev] = ptr;
+    return PM_OK;
+}
+
+void *static_scratch(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    return (dev >= 0 && dev < kMaxDevices) ? g_static_ptr[dev] : nullptr;
+}
+
+// Layout in the array: the instance table, the codes, the second field set.
+constexpr size_t kStaticTab = 1024;
+static_assert(4 * sizeof(InstDev) <= kStaticTab, "instance table region too small");
+size_t static_bytes_needed(int64_t N, size_t e)
+{
+    const size_t codes = ((size_t)N * 4 + 255) / 256 * 256;
+    return kStaticTab + codes + 4 * (size_t)N * e;
+}
+
+}  // namespace
+
 extern "C" {
 
 void pm_params_default(pm_params *p)
@@ -1700,7 +1748,8 @@ pm_status pm_create(int hip_device, size_t mem_cap_bytes, pm_ctx **out)
     ctx->dev = hip_device;
     ctx->cap = mem_cap_bytes;
     load_tune_cache(ctx);
-    if (hipSetDevice(hip_device) != hipSuccess) {
+    if (hipSetDevice(hip_device) != hipSuccess || static_scratch_setup(hip_device) != PM_OK) {
+        (void)hipGetLastError();
         delete ctx;
         return PM_ERR_DEVICE;
     }
@@ -1825,6 +1874,36 @@ pm_status pm_iterate(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx,
     // the scratch buffers are freed on return: finish the work that reads them
     PM_HIP(hipStreamSynchronize(s));
     stats_end(ctx);
+    return PM_OK;
+}
+
+pm_status pm_iterate_static(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz,
+                            int axis, const pm_params *params, void *u, void *v, void *w, void *p, int64_t count)
+{
+    if (!ctx) return PM_ERR_ARG;
+    ctx->err.clear();
+    void *f[4] = {u, v, w, p};
+    PM_TRY(check_iterate_args(ctx, mask, nx, ny, nz, axis, params, f, count));
+    const Prec prec = params->precision == PM_FP64 ? kF64 : kF32;
+    const int64_t N = nx * ny * nz;
+    const size_t need = static_bytes_needed(N, elem(prec));
+    if (need > (size_t)PM_STATIC_SCRATCH_BYTES)
+        return fail(ctx, PM_ERR_ARG,
+                    "pm_iterate_static: %lld voxels need %zu bytes of static scratch, more than its %zu "
+                    "(at most about %lld voxels in this precision); use pm_iterate",
+                    (long long)N, need, (size_t)PM_STATIC_SCRATCH_BYTES,
+                    (long long)(((size_t)PM_STATIC_SCRATCH_BYTES - kStaticTab - 256) / (4 + 4 * elem(prec))));
+    PM_TRY(set_device(ctx));
+    char *base = (char *)static_scratch(ctx->dev);
+    if (!base) return fail(ctx, PM_ERR_DEVICE, "static scratch of device %d was not set up", ctx->dev);
+    std::memset(&ctx->stats, 0, sizeof ctx->stats);
+    if (count == 0) return PM_OK;
+    InstDev *tab = (InstDev *)base;
+    void *codes = base + kStaticTab;
+    void *second = base + kStaticTab + ((size_t)N * 4 + 255) / 256 * 256;
+    PM_TRY(iterate_on(ctx, (hipStream_t)stream, mask, (int)nx, (int)ny, (int)nz, axis, params, f, count, codes,
+                      second, tab, false));
+    PM_HIP(hipStreamSynchronize((hipStream_t)stream));
     return PM_OK;
 }
 
