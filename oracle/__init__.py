@@ -38,15 +38,16 @@ class OrcParams(ctypes.Structure):
         ("check_every", ctypes.c_int32),
         ("warm_start", ctypes.c_int32),
         ("stop_rule", ctypes.c_int32),
-        ("pad", ctypes.c_int32),
+        ("fixed_pressure", ctypes.c_int32),
     ]
 
 
 def params(**kw) -> OrcParams:
     """Defaults: Re = 0.01 and c*^2 = 1.5e6 (§4 "Simulation parametrization"),
-    drive G = 1 per voxel, dt = 2^-12, tol = 1e-8, residual check every 100 sweeps."""
+    drive G = 1 per voxel, dt = 2^-12, tol = 1e-8, residual check every 100 sweeps,
+    periodic p~ along the load axis (fixed_pressure=1: held on the layer x_axis = 0)."""
     p = OrcParams(re=0.01, c2=1.5e6, dt=2.0**-12, tol=1e-8, drive=1.0, voxel_size=1.0,
-                  max_sweeps=10_000_000, check_every=100, warm_start=0, stop_rule=0, pad=0)
+                  max_sweeps=10_000_000, check_every=100, warm_start=0, stop_rule=0, fixed_pressure=0)
     for k, v in kw.items():
         setattr(p, k, v)
     return p

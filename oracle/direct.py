@@ -109,13 +109,14 @@ def _components(fluid: np.ndarray):
 class System:
     """Assembled discrete steady equations for one mask and load axis."""
 
-    def __init__(self, mask, axis: int, re: float = 0.01, drive: float = 1.0):
+    def __init__(self, mask, axis: int, re: float = 0.01, drive: float = 1.0, fixed_pressure: bool = False):
         S = np.ascontiguousarray(mask, dtype=bool)
         self.mask = S
         nz, ny, nx = S.shape
         N = S.size
         nu = 1.0 / re
         self.re, self.drive, self.axis = re, drive, axis
+        self.fixed_pressure = fixed_pressure
 
         def lin(x, y, z):
             return ((z % nz) * ny + (y % ny)) * nx + (x % nx)
@@ -137,11 +138,24 @@ class System:
             face_index.append(idx)
         fluid = ~S
         cell_index = -np.ones(N, dtype=np.int64)
-        fc = np.nonzero(fluid.reshape(-1))[0]
+        # pressure unknowns: every fluid cell, except (fixed pressure, §4) the
+        # cells of the layer x_axis = 0, whose p is held at 0 and whose mass
+        # balance is not imposed
+        unknown = fluid.copy()
+        if fixed_pressure:
+            layer = [slice(None)] * 3
+            layer[2 - axis] = 0
+            unknown[tuple(layer)] = False
+        fc = np.nonzero(unknown.reshape(-1))[0]
         cell_index[fc] = nF + np.arange(fc.size)
         nC = fc.size
         _, labels = _components(fluid)
-        fluid_comps = np.unique(labels[fc])
+        # a pore that reaches the fixed layer has its gauge fixed there; the
+        # others keep one multiplier and one gauge row each
+        held = np.zeros(labels.max() + 1 if labels.size else 0, dtype=bool)
+        if fixed_pressure:
+            held[np.unique(labels[(fluid & ~unknown).reshape(-1)])] = True
+        fluid_comps = np.array([c for c in np.unique(labels[fc]) if not held[c]], dtype=np.int64)
         comp_index = {c: nF + nC + i for i, c in enumerate(fluid_comps)}
         nL = len(fluid_comps)
         self.face_index, self.cell_index, self.fc = face_index, cell_index, fc
@@ -173,9 +187,9 @@ class System:
                         mr.append(row); mc.append(face_index[k][fid]); mv.append(nu * float(coef))
                 q = list(c)
                 q[k] -= 1
-                mr += [row, row]
-                mc += [cell_index[cid], cell_index[lin(*q)]]
-                mv += [-1.0, 1.0]
+                for cell, sign in ((cid, -1.0), (lin(*q), 1.0)):
+                    if cell_index[cell] >= 0:  # a held pressure is 0
+                        mr.append(row); mc.append(cell_index[cell]); mv.append(sign)
                 self.b[row] = drive if k == axis else 0.0
                 row += 1
         # momentum operator over [faces, cells]: F = Mom @ [v; p] + b
@@ -238,9 +252,10 @@ class System:
         # Lagrange multiplier of each pore in its mass rows, gauge rows sum p = 0
         comp_col = {c: nF + nC + i for i, c in enumerate(self.fluid_comps)}
         lab = self.labels[self.fc]
-        rows.append(nF + np.arange(nC))
-        cols.append(np.array([comp_col[c] for c in lab], dtype=np.int64))
-        vals.append(np.ones(nC))
+        gauged = np.array([c in comp_col for c in lab], dtype=bool)
+        rows.append(nF + np.arange(nC)[gauged])
+        cols.append(np.array([comp_col[c] for c in lab[gauged]], dtype=np.int64))
+        vals.append(np.ones(int(gauged.sum())))
         for i, c in enumerate(self.fluid_comps):
             members = np.nonzero(lab == c)[0]
             rows.append(np.full(members.size, nF + nC + i))
@@ -254,10 +269,11 @@ class System:
         return sol[:nF + nC], sol[nF + nC:]
 
 
-def solve_steady(mask, axis: int, re: float = 0.01, drive: float = 1.0):
+def solve_steady(mask, axis: int, re: float = 0.01, drive: float = 1.0, fixed_pressure: bool = False):
     """Discrete steady state for load axis `axis`: returns (kcol, u, v, w, p, lambda).
-    kcol[i] = q_i / (Re G), q_i the mean of v_i over all i-faces (App. C)."""
-    sysm = System(mask, axis, re, drive)
+    kcol[i] = q_i / (Re G), q_i the mean of v_i over all i-faces (App. C).
+    fixed_pressure: p held at 0 on the layer x_axis = 0 (§4), no mass rows there."""
+    sysm = System(mask, axis, re, drive, fixed_pressure)
     x, lam = sysm.solve()
     u, v, w, p = sysm.unpack(x)
     N = sysm.mask.size

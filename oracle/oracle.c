@@ -23,7 +23,12 @@
  *     the momentum equation of the load-axis component (§4 "Simulation
  *     parametrization": initial gradient 1/vx, Re = 0.01, c*^2 = 1.5e6);
  *   - Darcy (§4 eq. darcy, App. C): k_{i,axis} = dx^2 q_i / (Re G), q_i the
- *     mean of u_i over all i-faces.
+ *     mean of u_i over all i-faces;
+ *   - optional fixed pressure in the main flow direction (§4 "Boundary in the
+ *     numerically considered domain", Fig. 2 p_in / p_out): p~ held on the
+ *     cell layer x_axis = 0, so that p = p_in there and p_out = p_in - G n
+ *     one period later; that layer's mass balance is not imposed and it is
+ *     left out of the residual's divergence sum.
  *
  * Floating point: FP64, terms summed in the written order (x, then y, then
  * z), built without fast-math or FMA contraction.
@@ -44,7 +49,11 @@ typedef struct {
     int32_t check_every;
     int32_t warm_start; /* 1: start from the given fields               */
     int32_t stop_rule;  /* 0: residual r, 1: relative flux change eps_q */
-    int32_t pad;
+    int32_t fixed_pressure; /* 1: §4 "in main flow direction we employ fixed
+                           pressure conditions", read as: p~ is held at its
+                           value (0 from rest) on the cell layer x_axis = 0,
+                           whose mass balance is not imposed; the velocity
+                           stays periodic ("periodic for the local flux") */
 } orc_params;
 
 enum { ORC_OK = 0, ORC_ERR_ARG = 1, ORC_ERR_OOM = 2, ORC_NOT_CONVERGED = 4, ORC_DIVERGED = 5,
@@ -224,7 +233,10 @@ void orc_sweep(const orc_params *prm, const uint8_t *fs, int64_t nx, int64_t ny,
             for (int64_t x = 0; x < nx; ++x) {
                 int64_t c[3] = {x, y, z};
                 int64_t id = (z * ny + y) * nx + x;
-                p2[id] = p[id] - c2 * dt * divergence(&g, fs, vnew, c);
+                if (prm->fixed_pressure && c[axis] == 0)
+                    p2[id] = p[id];  /* fixed-pressure layer */
+                else
+                    p2[id] = p[id] - c2 * dt * divergence(&g, fs, vnew, c);
             }
 }
 
@@ -263,14 +275,14 @@ void orc_sweep_points(const orc_params *prm, const uint8_t *fs, int64_t nx, int6
         out[4 * m + 0] = vn[0];
         out[4 * m + 1] = vn[1];
         out[4 * m + 2] = vn[2];
-        out[4 * m + 3] = p[id] - c2 * dt * div;
+        out[4 * m + 3] = (prm->fixed_pressure && c[axis] == 0) ? p[id] : p[id] - c2 * dt * div;
     }
 }
 
 /*
  * Residual sums and fluxes of a state (v, p):
  *   out[0] = S_F = sum over fluid faces of F_k(v, p)^2
- *   out[1] = S_D = sum over cells of (nu div v)^2
+ *   out[1] = S_D = sum over cells of (nu div v)^2 (not over a fixed-pressure layer)
  *   out[2+k] = Q_k = sum over all k-faces of v_k (solid faces are zero)
  */
 void orc_state_sums(const orc_params *prm, const uint8_t *fs, int64_t nx, int64_t ny, int64_t nz,
@@ -293,6 +305,7 @@ void orc_state_sums(const orc_params *prm, const uint8_t *fs, int64_t nx, int64_
                     SF += F * F;
                     Q[k] += vin[k][id];
                 }
+                if (prm->fixed_pressure && c[axis] == 0) continue;  /* no mass balance there */
                 double d = nu * divergence(&g, fs, vin, c);
                 SD += d * d;
             }

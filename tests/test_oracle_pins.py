@@ -429,3 +429,95 @@ def test_outer_walls_duct_sylvester(H, W):
     assert r.status == "OK"
     assert r.kcol[0] == pytest.approx(want, rel=1e-9)
     assert r.state.u.shape == m.shape
+
+
+# ------------------------------------------------------------ fixed pressure (§4)
+#
+# Reading of §4 "in main flow direction we employ fixed pressure conditions"
+# with a flux that stays periodic: p~ is held on the cell layer x_axis = 0
+# (p = p_in there, p_out = p_in - G n one period later) and that layer's mass
+# balance is not imposed.
+
+@pytest.mark.parametrize("mi", range(4))
+def test_fixed_pressure_sweep_equals_assembled_affine_map(mi):
+    mask = small_masks()[mi]
+    prm = oracle.params(fixed_pressure=1)
+    for axis in range(3):
+        st = random_state(mask, 200 + mi)
+        sl = [slice(None)] * 3
+        sl[2 - axis] = 0
+        st.p[tuple(sl)] = 0.0  # the held value (0 from rest); the assembled map has p = 0 there
+        got = oracle.sweep(mask, axis, st, prm)
+        sysm = direct.System(mask, axis, re=prm.re, drive=prm.drive, fixed_pressure=True)
+        want = sysm.sweep(st.u, st.v, st.w, st.p, prm.dt, prm.c2)
+        for g, w in zip(got.arrays(), want):
+            assert np.abs(g - w).max() / max(np.abs(w).max(), 1e-300) < 1e-13
+        # the held layer keeps its pressure exactly
+        assert np.array_equal(got.p[tuple(sl)], st.p[tuple(sl)])
+
+
+@pytest.mark.parametrize("mi", range(4))
+def test_fixed_pressure_converged_k_equals_direct_solve(mi):
+    mask = small_masks()[mi]
+    prm = oracle.params(tol=1e-12, fixed_pressure=1)
+    sols = [direct.solve_steady(mask, axis, fixed_pressure=True) for axis in range(3)]
+    kscale = max(np.abs(s[0]).max() for s in sols)
+    for axis in range(3):
+        kd, ud, vd, wd, pd, lam = sols[axis]
+        r = oracle.solve(mask, axis, prm)
+        assert r.status == "OK"
+        assert np.abs(r.kcol - kd).max() / kscale < 1e-9, (axis, r.kcol, kd)
+        vscale = max(np.abs(f).max() for sol in sols for f in sol[1:4])
+        for g, w in zip(r.state.arrays(), (ud, vd, wd, pd)):
+            assert np.abs(g - w).max() / max(np.abs(w).max(), vscale) < 1e-7
+
+
+@pytest.mark.parametrize("n,s", [(1, 1), (3, 2), (5, 3)])
+def test_fixed_pressure_plane_poiseuille_closed_form(n, s):
+    """A channel along the drive has a uniform pressure in every cross-section,
+    so holding it on one layer changes nothing: the same discrete closed form."""
+    L = n + s
+    want = (n * n / 12.0 + 1.0 / 24.0) * n / L
+    prm = oracle.params(tol=1e-11, fixed_pressure=1)
+    for wall_axis, flow_axis in [(1, 0), (2, 1), (0, 2)]:
+        shape = [4, 4, 4]
+        shape[2 - wall_axis] = L
+        m = np.zeros(shape, dtype=np.uint8)
+        sl = [slice(None)] * 3
+        sl[2 - wall_axis] = slice(n, L)
+        m[tuple(sl)] = 1
+        r = oracle.solve(m, flow_axis, prm)
+        assert r.status == "OK"
+        assert r.kcol[flow_axis] == pytest.approx(want, rel=1e-9)
+        others = [k for k in range(3) if k != flow_axis]
+        assert np.abs(r.kcol[others]).max() < 1e-12 * want
+
+
+def test_fixed_pressure_flux_constant_across_slices():
+    """Every layer but the held one balances its mass; with a periodic flux the
+    held layer's net source is then zero as well, so at the fixed point every
+    slice normal to the drive carries the same flux (the held layer only
+    redistributes it across the section)."""
+    mask = synth.spheres(9, 8, 10, 1.8, 2.4, 0.55, 33)
+    for axis in range(3):
+        r = oracle.solve(mask, axis, oracle.params(tol=1e-12, fixed_pressure=1))
+        assert r.status == "OK"
+        qs = oracle.slice_flux(mask, r.state)
+        n = mask.shape[2 - axis]
+        q = qs[axis, :n]
+        assert np.abs(q - q.mean()).max() < 1e-8 * np.abs(q).max()
+        assert q.mean() / (mask.size / n) == pytest.approx(r.hist_q[-1][axis], rel=1e-9)
+
+
+def test_fixed_pressure_reflection_and_difference_from_periodic():
+    """Reflecting a transverse axis flips the sign of the coupling (the held
+    layer maps to itself); the held layer does change k on a mask whose
+    sections are not uniform."""
+    mask = synth.spheres(9, 8, 7, 1.8, 2.4, 0.55, 34)
+    prm = oracle.params(tol=1e-11, fixed_pressure=1)
+    a = oracle.solve(mask, 2, prm)
+    b = oracle.solve(np.ascontiguousarray(mask[:, ::-1, :]), 2, prm)
+    assert b.kcol[2] == pytest.approx(a.kcol[2], rel=1e-8)
+    assert b.kcol[1] == pytest.approx(-a.kcol[1], rel=1e-6, abs=1e-12)
+    per = oracle.solve(mask, 2, oracle.params(tol=1e-11))
+    assert abs(per.kcol[2] - a.kcol[2]) > 1e-4 * abs(a.kcol[2])
