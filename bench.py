@@ -141,6 +141,47 @@ def cpu_baseline(mask, seconds: float):
             "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
 
 
+def two_step_measure(ctx, mask_np, mask, args) -> dict:
+    """The two-step kernel (two fused sweeps per read and write of the fields)
+    against the single-step one on the same grid: per-launch time, effective
+    sweep rate, algorithmic bytes per pass over the launch time (HBM fraction),
+    and the effective rate over the single-sweep roofline (above 1 possible)."""
+    import torch
+
+    import paper_2407_19868_amd as ps
+    N = mask_np.size
+    res = {}
+    for form, prec in (("fp32", ps.FP32), ("fp64", ps.FP64)):
+        dt = torch.float32 if prec == ps.FP32 else torch.float64
+        f = list(ps.field_set(mask_np.shape, dt))
+        bpv = BYTES_PER_VOXEL[form]
+        ctx.iterate(mask, 0, f, 21, ps.params(precision=prec, tblock=2))  # warm-up
+        ctx.iterate(mask, 0, f, 201, ps.params(precision=prec, tblock=2))
+        st = ctx.last_stats()
+        us2 = st["t2_ms"] * 1e3 / max(st["t2_launches"], 1)
+        ctx.iterate(mask, 0, f, 201, ps.params(precision=prec, tblock=1))
+        st1 = ctx.last_stats()
+        us1 = st1["sweep_ms"] * 1e3 / max(st1["sweep_launches"], 1)
+        eff = 2 * N / (us2 * 1e-6) / 1e9
+        achieved = bpv * N / (us2 * 1e-6) / 1e9
+        res[form] = {"kernel": f"k_fused2<{'double' if prec == ps.FP64 else 'float'},64,8>",
+                     "avg_launch_us": round(us2, 2), "sweeps_per_launch": 2,
+                     "gvox_per_s_effective": round(eff, 2),
+                     "hbm_achieved_gbs": round(achieved, 1), "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "effective_over_single_sweep_roofline": round(eff * bpv / HBM_PEAK_GBS, 4),
+                     "single_step_same_grid": {"avg_launch_us": round(us1, 2),
+                                               "gvox_per_s": round(N / (us1 * 1e-6) / 1e9, 2)},
+                     "speedup_vs_single_step": round(2 * us1 / us2, 3)}
+        log(f"[bench] two-step {form}: {us2:.1f} us per launch, {eff:.1f} GVox/s effective "
+            f"(single step {N / us1 / 1e3:.1f}), {100 * achieved / HBM_PEAK_GBS:.1f}% HBM per pass")
+        del f
+        torch.cuda.empty_cache()
+    res["note"] = ("algorithmic bytes per pass (one read and write of the four fields and the face flags) over "
+                   "the launch time; the effective rate counts two sweeps per pass and may exceed the "
+                   "single-sweep roofline")
+    return res
+
+
 def k_error_table(k, ref) -> dict:
     """Entry-wise error of a 3x3 tensor against a reference: |dk_ij| / |ref_ij|
     (relative) and |dk_ij| / max |ref| (normwise, meaningful for the small
@@ -228,13 +269,32 @@ def series_workload(args) -> dict:
             log(f"[bench] decay: r {rr[-1]:.3e} after {r.sweeps} sweeps, {1000 * rate:.3f} e-folds/1000 sweeps")
             del f
             torch.cuda.empty_cache()
+        tensor = None
+        if args.tensor_sweeps > 0:
+            # the full tensor call at this size: the three load cases do not fit beside
+            # each other and run one after another inside pm_tensor
+            ctx.trim()
+            log(f"[bench] 1536^3 tensor, FP32-DC, {args.tensor_sweeps} sweeps per load axis")
+            t0 = time.perf_counter()
+            tr = ctx.tensor(mask, ps.params(precision=ps.FP32_DC, max_sweeps=args.tensor_sweeps, progress=10))
+            wall = time.perf_counter() - t0
+            st = ctx.last_stats()
+            tensor = {"status": tr.status, "sweeps": [int(x) for x in tr.sweeps], "seconds": round(wall, 1),
+                      "cases_at_once": int(st["tensor_cases_at_once"]),
+                      "dc_promoted_for_memory": int(st["dc_promoted_for_memory"]),
+                      "library_peak_bytes": int(st["peak_bytes"]),
+                      "r_last": [float(h["r"][-1]) if len(h["r"]) else None for h in tr.hists],
+                      "k": [[float(f"{x:.8g}") for x in row] for row in tr.k],
+                      "note": "a sweep budget, not convergence: k is that of the last check"}
+            log(f"[bench] 1536^3 tensor: {wall:.1f} s, status {tr.status}, cases at once "
+                f"{st['tensor_cases_at_once']}, r {tensor['r_last']}")
         ctx.close()
         return {"metric": "GVoxel-updates/s per sweep (% HBM roofline)", "value": res["fp32"]["gvox_per_s_kernel"],
                 "unit": "GVoxel-updates/s", "dtype": "f32", "data": "synthetic",
                 "config": {"workload": "overlapping spheres 1536^3, radius U[5,12], porosity 0.20, seed 5; "
                                        "load axis x; fields from rest",
                            "grid": [1536, 1536, 1536], "porosity": round(float(1 - mask_np.mean()), 4)},
-                "forms": res, "residual_decay": decay}
+                "forms": res, "residual_decay": decay, "tensor": tensor}
 
     if args.workload == "precipitation":
         log("[bench] generating the precipitation series (16 states, 1024x512x16 + walls)")
@@ -334,6 +394,8 @@ def main() -> int:
                     help="sweep budget of the series solves (--workload precipitation/foam)")
     ap.add_argument("--compare-sweeps", type=int, default=0,
                     help="series workloads: also time this many sweeps per instance batched vs sequential")
+    ap.add_argument("--tensor-sweeps", type=int, default=0,
+                    help="spheres1536: also call pm_tensor (FP32-DC) with this sweep budget per load axis")
     ap.add_argument("--decay-sweeps", type=int, default=0,
                     help="spheres1536: FP32 solve of this many sweeps to extrapolate the sweeps to r < 1e-8")
     ap.add_argument("--pore-cleanup", type=int, choices=[0, 1], default=0,
@@ -446,6 +508,10 @@ def main() -> int:
                      "roofline": o_roof, "tile": o_tile,
                      "single_sweep_roofline_gvox": round(HBM_PEAK_GBS / BYTES_PER_VOXEL[other_form], 1)},
     }
+
+    # two sweeps per HBM pass (tblock 2): the two-step kernel on the same packing,
+    # one load axis, timed with HIP events around its consecutive launches
+    out["two_step"] = two_step_measure(ctx, mask_np, mask, args)
 
     if not args.no_tensor:
         tt = {}

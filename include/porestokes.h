@@ -142,6 +142,14 @@ typedef struct {
     int32_t tile2_y;    /* (tile2_x, tile2_y) one of 64x10, 64x8, 64x6, 32x24, 32x12,
                            32x8                                                      */
     int32_t zchunk2;    /* planes per two-sweep workgroup along z (0 = auto)         */
+    int32_t fixed_pressure; /* §4 "in main flow direction we employ fixed pressure
+                           conditions" (Fig. 2: p_in, p_out), with the flux kept
+                           periodic: 1 holds p~ on the cell layer x_axis = 0 at
+                           its starting value (0 from rest), so the pressure is
+                           p_in there and p_out = p_in - G n one period later;
+                           that layer's mass balance is not imposed and its
+                           cells are left out of the residual's divergence sum.
+                           0: p~ periodic and free everywhere.     default 0        */
 } pm_params;
 
 /* Residual history: one record per check.  Host arrays of length cap owned by

@@ -61,6 +61,7 @@ class PmParams(ctypes.Structure):
         ("tile2_x", ctypes.c_int32),
         ("tile2_y", ctypes.c_int32),
         ("zchunk2", ctypes.c_int32),
+        ("fixed_pressure", ctypes.c_int32),
     ]
 
 

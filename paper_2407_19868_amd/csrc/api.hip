@@ -244,6 +244,8 @@ pm_status check_params(pm_ctx *ctx, const pm_params *p)
             return fail(ctx, PM_ERR_ARG, "unsupported two-sweep tile %dx%d", p->tile2_x, p->tile2_y);
     }
     if (p->zchunk2 < 0) return fail(ctx, PM_ERR_ARG, "zchunk2 must be >= 0");
+    if (p->fixed_pressure != 0 && p->fixed_pressure != 1)
+        return fail(ctx, PM_ERR_ARG, "fixed_pressure must be 0 or 1");
     return PM_OK;
 }
 
@@ -367,17 +369,14 @@ int auto_zc2(int nx, int ny, int nz, int ox, int oy)
     return std::min(best, nz);
 }
 
-// Default output tile of the two-step kernel: FP32 64 x 10 (68 x 14 threads),
-// FP64 32 x 12 (36 x 16 threads: the FP64 windows of a larger workgroup spill).
+// Default output tile of the two-step kernel: 64 x 8 (68 x 12 threads) in both
+// precisions, the fastest of 64x10, 64x8, 64x6, 32x24, 32x12 and 32x8 on the
+// 256^3 packing (FP32 262 us, FP64 450 us per two-sweep launch).
 void default_tile2(Prec prec, int *ox, int *oy)
 {
-    if (prec == kF64) {
-        *ox = 32;
-        *oy = 12;
-    } else {
-        *ox = 64;
-        *oy = 10;
-    }
+    (void)prec;
+    *ox = 64;
+    *oy = 8;
 }
 
 TileCfg pick_tiles(pm_ctx *ctx, const pm_params *prm, int nx, int ny, int nz, Prec prec)
@@ -535,6 +534,8 @@ InstDev make_dev(const Inst &in, const pm_params *prm, int64_t blk_begin, bool s
         d.src[f] = in.delta ? (const char *)in.dsrc + (size_t)f * in.N * sizeof(float) : nullptr;
     d.rdt = 1.0 / prm->dt;
     d.rc2dt = 1.0 / (prm->c2 * prm->dt);
+    d.fixp = prm->fixed_pressure;
+    d.pad = 0;
     return d;
 }
 
@@ -1563,7 +1564,7 @@ pm_status iterate_on(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx, in
         for (int64_t n = 0; n < count; ++n) {
             const int a = (int)(n & 1);
             PM_HIP(launch_simple_sweep(prec, nx, ny, nz, axis, (const uint32_t *)codes, set[a], set[a ^ 1], nu,
-                                       params->dt, c2dt, params->drive, s));
+                                       params->dt, c2dt, params->drive, params->fixed_pressure, s));
         }
         if (timed) PM_TRY(stats_mark(ctx, s, false, 2 * count, count * N));
         if (count & 1)
@@ -1932,7 +1933,7 @@ pm_status pm_residual(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx
     PM_HIP(launch_face_codes(mask, (int)nx, (int)ny, (int)nz, (uint32_t *)codes, s));
     int64_t nb = 0;
     PM_HIP(launch_state_sums(prec, (int)nx, (int)ny, (int)nz, axis, (const uint32_t *)codes, f, 1.0 / params->re,
-                             params->drive, (double *)part, &nb, s));
+                             params->drive, params->fixed_pressure, (double *)part, &nb, s));
     PartialRef r{(const double *)part, nb};
     PM_HIP(hipMemcpyAsync(refs, &r, sizeof r, hipMemcpyHostToDevice, s));
     PM_HIP(launch_reduce_partials((const PartialRef *)refs, 1, (double *)sums, s));

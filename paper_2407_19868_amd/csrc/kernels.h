@@ -27,6 +27,8 @@ struct InstDev {
     // them into the residual sums
     const void *src[4];
     double rdt, rc2dt;
+    int32_t fixp;        // 1: p~ held on the cell layer x_axis = 0 (fixed pressure)
+    int32_t pad;
 };
 
 // Write n <= 3 table entries to device memory from the launch arguments (no
@@ -92,15 +94,16 @@ bool fused_tile_supported(int tile_x, int tile_y, int prec);
 // Final deterministic reduction: out[i * kNumSums + j] = sum over blocks of refs[i].
 hipError_t launch_reduce_partials(const PartialRef *refs, int ninst, double *out, hipStream_t s);
 
-// Two-pass reference sweep (velocity, then pressure), one thread per cell.
+// Two-pass reference sweep (velocity, then pressure), one thread per cell;
+// fixp: p~ held on the cell layer x_axis = 0.
 hipError_t launch_simple_sweep(Prec prec, int nx, int ny, int nz, int axis, const uint32_t *codes,
                                const void *const in[4], void *const out[4], double nu, double dt,
-                               double c2dt, double drive, hipStream_t s);
+                               double c2dt, double drive, int fixp, hipStream_t s);
 
 // Residual sums of a state into partials (one row of kNumSums per block);
 // returns the number of blocks used through *nblocks.
 hipError_t launch_state_sums(Prec prec, int nx, int ny, int nz, int axis, const uint32_t *codes,
-                             const void *const st[4], double nu, double drive, double *partials,
+                             const void *const st[4], double nu, double drive, int fixp, double *partials,
                              int64_t *nblocks, hipStream_t s);
 int64_t state_sums_blocks(int64_t n);
 

@@ -435,6 +435,25 @@ __device__ __forceinline__ int64_t next_plane(int64_t zb, int64_t plane_b, int64
     return n == field_b ? 0 : n;
 }
 
+// Fixed pressure (InstDev::fixp): p~ is held on the cell layer x_axis = 0.  A
+// thread computes p^n of its own cell and of its -x and -y neighbours; each
+// is held when it lies in that layer.  For the z axis that is a property of
+// the plane (uniform): the plane at byte offset 0.
+struct HeldLayer {
+    bool own = false, xm = false, ym = false, fixz = false;
+    __device__ __forceinline__ HeldLayer(const InstDev &I, int gx, int gy)
+    {
+        if (!I.fixp) return;
+        const int xw = wrap_int(gx, I.nx), yw = wrap_int(gy, I.ny);
+        const int xmw = wrap_int(gx - 1, I.nx), ymw = wrap_int(gy - 1, I.ny);
+        own = (I.axis == 0 && xw == 0) || (I.axis == 1 && yw == 0);
+        xm = (I.axis == 0 && xmw == 0) || (I.axis == 1 && yw == 0);
+        ym = (I.axis == 0 && xw == 0) || (I.axis == 1 && ymw == 0);
+        fixz = I.axis == 2;
+    }
+    __device__ __forceinline__ bool plane(int64_t zb) const { return fixz && zb == 0; }
+};
+
 template <typename T, int TX, int TY>
 struct FusedShared {
     static constexpr int PX = TX + 4, PY = TY + 4, PP = PX * PY;
@@ -553,6 +572,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
     const int gx = x0 + tx, gy = y0 + ty;
     const bool active = gx < nx && gy < ny;
     const int own = wrap_int(gy, ny) * nx + wrap_int(gx, nx);
+    const HeldLayer held(I, gx, gy);
     const uint32_t own_b = (uint32_t)own * (uint32_t)sizeof(T), own_c = (uint32_t)own * 4u;
     const int cl = (ty + 2) * PX + (tx + 2);  // own position in the padded plane
 
@@ -671,17 +691,18 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
         __syncthreads();
 
         // ---- p^n of the own cell
+        const bool hz = held.plane(zb0);
         const T dvg = divergence(Uw[2], su[cl + 1], Vw[2], sv[cl + PX], Ww[1], Ww[2]);
-        const T pn = skip ? pold : fma(-c2dt, dvg, pold);
+        const T pn = (skip || held.own || hz) ? pold : fma(-c2dt, dvg, pold);
 
         if constexpr (body) {
             // lanes outside the grid hold a wrapped column: they compute and
             // store exactly the values of that column's own lane
             // p^n of the -x and -y neighbours, from the staged planes
             const T dxm = divergence(su[cl - 1], Uw[2], sv[cl - 1], sv[cl - 1 + PX], swc[cl - 1], swn[cl - 1]);
-            const T pxm = skip ? sp[cl - 1] : fma(-c2dt, dxm, sp[cl - 1]);
+            const T pxm = (skip || held.xm || hz) ? sp[cl - 1] : fma(-c2dt, dxm, sp[cl - 1]);
             const T dym = divergence(su[cl - PX], su[cl - PX + 1], sv[cl - PX], Vw[2], swc[cl - PX], swn[cl - PX]);
-            const T pym = skip ? sp[cl - PX] : fma(-c2dt, dym, sp[cl - PX]);
+            const T pym = (skip || held.ym || hz) ? sp[cl - PX] : fma(-c2dt, dym, sp[cl - PX]);
             bstore<T, kNonTemporal>(SRC ? pn + sP : pn, rsrc_at(Pout, zb0, plane_b), own_b);
             // u: own axis x, across y (LDS) and z (registers)
             const uint32_t cu = code;
@@ -714,11 +735,12 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
             const bool sw_ = (cw & kSolidBit) != 0;
             bstore<T, kNonTemporal>(sw_ ? T(0) : (SRC ? fma(dt, Fw, w0) + sW : fma(dt, Fw, w0)),
                                     rsrc_at(Wout, zb0, plane_b), own_b);
+            // a held cell's mass balance is not imposed: no divergence term
             if (RED && !SRC && active) {
                 const double fu = su_ ? 0.0 : (double)Fu, fv = sv_ ? 0.0 : (double)Fv,
                              fw = sw_ ? 0.0 : (double)Fw;
                 acc[0] += fu * fu + fv * fv + fw * fw;
-                const double nd = (double)(nu * dvg);
+                const double nd = (held.own || hz) ? 0.0 : (double)(nu * dvg);
                 acc[1] += nd * nd;
             }
             if (RED && SRC && active) {
@@ -726,7 +748,8 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
                 const double fv = sv_ ? 0.0 : fma((double)sV, I.rdt, (double)Fv);
                 const double fw = sw_ ? 0.0 : fma((double)sW, I.rdt, (double)Fw);
                 acc[0] += fu * fu + fv * fv + fw * fw;
-                const double nd = (double)nu * fma(-(double)sP, I.rc2dt, (double)dvg);
+                const double nd =
+                    (held.own || hz) ? 0.0 : (double)nu * fma(-(double)sP, I.rc2dt, (double)dvg);
                 acc[1] += nd * nd;
             }
             if (RED && active) {
@@ -880,6 +903,7 @@ k_fused2(const InstDev *__restrict__ insts, int ninst, int parity)
     // ---- own column (wrapped: the region may reach across the periodic boundary)
     const bool is_out = tx >= 2 && tx < SX - 2 && ty >= 2 && ty < SY - 2;
     const int own = wrap_int(Y1 + ty, ny) * nx + wrap_int(X1 + tx, nx);
+    const HeldLayer held(I, X1 + tx, Y1 + ty);
     const uint32_t own_b = (uint32_t)own * (uint32_t)sizeof(T), own_c = (uint32_t)own * 4u;
     // stores: output lanes at their column (lanes of a column beyond the grid
     // store the identical values of the wrapped column); ring lanes beyond the
@@ -999,13 +1023,14 @@ k_fused2(const InstDev *__restrict__ insts, int ninst, int parity)
         }
         __syncthreads();
 
+        const bool hz = held.plane(zb0);
         const T dvg = divergence(Uw[2], su[cl + 1], Vw[2], sv[cl + PX], Ww[1], Ww[2]);
-        const T pn = fma(-c2dt, dvg, pold);
+        const T pn = (held.own || hz) ? pold : fma(-c2dt, dvg, pold);
         if constexpr (body) {
             const T dxm = divergence(su[cl - 1], Uw[2], sv[cl - 1], sv[cl - 1 + PX], swc[cl - 1], swn[cl - 1]);
-            const T pxm = fma(-c2dt, dxm, sp[cl - 1]);
+            const T pxm = (held.xm || hz) ? sp[cl - 1] : fma(-c2dt, dxm, sp[cl - 1]);
             const T dym = divergence(su[cl - PX], su[cl - PX + 1], sv[cl - PX], Vw[2], swc[cl - PX], swn[cl - PX]);
-            const T pym = fma(-c2dt, dym, sp[cl - PX]);
+            const T pym = (held.ym || hz) ? sp[cl - PX] : fma(-c2dt, dym, sp[cl - PX]);
             const uint32_t cu = code;
             const T u0 = Uw[2];
             const T u_d2x = d2_own(su[cl - 1], u0, su[cl + 1]);
@@ -1089,19 +1114,20 @@ k_fused2(const InstDev *__restrict__ insts, int ninst, int parity)
         sp[c2] = P1[0];
         swn[c2] = W1[2];
         __syncthreads();
+        const bool hz = held.plane(zout);
         T pn = T(0);
         if (is_out) {
             const T dvg = divergence(U1[2], su[c2 + 1], V1[2], sv[c2 + SX], W1[1], W1[2]);
-            pn = fma(-c2dt, dvg, P1[0]);
+            pn = (held.own || hz) ? P1[0] : fma(-c2dt, dvg, P1[0]);
         }
         if constexpr (body) {
             T ru = T(0), rv = T(0), rw = T(0);
             if (is_out) {
                 const T dxm = divergence(su[c2 - 1], U1[2], sv[c2 - 1], sv[c2 - 1 + SX], swc[c2 - 1], swn[c2 - 1]);
-                const T pxm = fma(-c2dt, dxm, sp[c2 - 1]);
+                const T pxm = (held.xm || hz) ? sp[c2 - 1] : fma(-c2dt, dxm, sp[c2 - 1]);
                 const T dym =
                     divergence(su[c2 - SX], su[c2 - SX + 1], sv[c2 - SX], V1[2], swc[c2 - SX], swn[c2 - SX]);
-                const T pym = fma(-c2dt, dym, sp[c2 - SX]);
+                const T pym = (held.ym || hz) ? sp[c2 - SX] : fma(-c2dt, dym, sp[c2 - SX]);
                 const uint32_t cu = C1[0];
                 const T u0 = U1[2];
                 const T u_d2x = d2_own(su[c2 - 1], u0, su[c2 + 1]);
@@ -1338,21 +1364,24 @@ __global__ void k_simple_vel(int nx, int ny, int nz, int axis, const uint32_t *_
 }
 
 template <typename T>
-__global__ void k_simple_pres(int nx, int ny, int nz, const T *__restrict__ U, const T *__restrict__ V,
-                              const T *__restrict__ W, const T *__restrict__ P, T *__restrict__ Po, T c2dt)
+__global__ void k_simple_pres(int nx, int ny, int nz, int axis, int fixp, const T *__restrict__ U,
+                              const T *__restrict__ V, const T *__restrict__ W, const T *__restrict__ P,
+                              T *__restrict__ Po, T c2dt)
 {
     const int64_t n = (int64_t)nx * ny * nz;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int x = (int)(t % nx), y = (int)((t / nx) % ny), z = (int)(t / ((int64_t)nx * ny));
+    const int c[3] = {x, y, z};
     const T d = divergence(U[t], ld(U, nx, ny, nz, x + 1, y, z), V[t], ld(V, nx, ny, nz, x, y + 1, z), W[t],
                            ld(W, nx, ny, nz, x, y, z + 1));
-    Po[t] = fma(-c2dt, d, P[t]);
+    Po[t] = (fixp && c[axis] == 0) ? P[t] : fma(-c2dt, d, P[t]);  // held layer
 }
 
 template <typename T>
 static hipError_t simple_sweep_t(int nx, int ny, int nz, int axis, const uint32_t *codes, const void *const in[4],
-                                 void *const out[4], double nu, double dt, double c2dt, double drive, hipStream_t s)
+                                 void *const out[4], double nu, double dt, double c2dt, double drive, int fixp,
+                                 hipStream_t s)
 {
     const int64_t n = (int64_t)nx * ny * nz;
     hipLaunchKernelGGL(k_simple_vel<T>, dim3(grid1d(n, 256)), dim3(256), 0, s, nx, ny, nz, axis, codes,
@@ -1360,17 +1389,18 @@ static hipError_t simple_sweep_t(int nx, int ny, int nz, int axis, const uint32_
                        (T *)out[1], (T *)out[2], (T)nu, (T)dt, (T)drive);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_simple_pres<T>, dim3(grid1d(n, 256)), dim3(256), 0, s, nx, ny, nz, (const T *)out[0],
-                       (const T *)out[1], (const T *)out[2], (const T *)in[3], (T *)out[3], (T)c2dt);
+    hipLaunchKernelGGL(k_simple_pres<T>, dim3(grid1d(n, 256)), dim3(256), 0, s, nx, ny, nz, axis, fixp,
+                       (const T *)out[0], (const T *)out[1], (const T *)out[2], (const T *)in[3], (T *)out[3],
+                       (T)c2dt);
     return hipGetLastError();
 }
 
 hipError_t launch_simple_sweep(Prec prec, int nx, int ny, int nz, int axis, const uint32_t *codes,
                                const void *const in[4], void *const out[4], double nu, double dt, double c2dt,
-                               double drive, hipStream_t s)
+                               double drive, int fixp, hipStream_t s)
 {
-    return prec == kF64 ? simple_sweep_t<double>(nx, ny, nz, axis, codes, in, out, nu, dt, c2dt, drive, s)
-                        : simple_sweep_t<float>(nx, ny, nz, axis, codes, in, out, nu, dt, c2dt, drive, s);
+    return prec == kF64 ? simple_sweep_t<double>(nx, ny, nz, axis, codes, in, out, nu, dt, c2dt, drive, fixp, s)
+                        : simple_sweep_t<float>(nx, ny, nz, axis, codes, in, out, nu, dt, c2dt, drive, fixp, s);
 }
 
 // ============================================================== state sums
@@ -1390,7 +1420,7 @@ int64_t state_sums_blocks(int64_t n)
 template <typename T>
 __global__ void k_state_sums(int nx, int ny, int nz, int axis, const uint32_t *__restrict__ codes,
                              const T *__restrict__ U, const T *__restrict__ V, const T *__restrict__ W,
-                             const T *__restrict__ P, T nu, T drive, double *__restrict__ partials)
+                             const T *__restrict__ P, T nu, T drive, int fixp, double *__restrict__ partials)
 {
     __shared__ double scratch[kNumSums * (kSumsBlock / 64)];
     const int64_t n = (int64_t)nx * ny * nz;
@@ -1427,6 +1457,8 @@ __global__ void k_state_sums(int nx, int ny, int nz, int axis, const uint32_t *_
             const T F = momentum(d2[0], d2[1], d2[2], pc, pm, nu, k == axis ? drive : T(0));
             acc[0] += (double)F * (double)F;
         }
+        const int cc[3] = {x, y, z};
+        if (fixp && cc[axis] == 0) continue;  // held layer: no mass balance
         const T d = divergence(U[t], ld(U, nx, ny, nz, x + 1, y, z), V[t], ld(V, nx, ny, nz, x, y + 1, z), W[t],
                                ld(W, nx, ny, nz, x, y, z + 1));
         const double nd = (double)(nu * d);
@@ -1436,8 +1468,8 @@ __global__ void k_state_sums(int nx, int ny, int nz, int axis, const uint32_t *_
 }
 
 hipError_t launch_state_sums(Prec prec, int nx, int ny, int nz, int axis, const uint32_t *codes,
-                             const void *const st[4], double nu, double drive, double *partials, int64_t *nblocks,
-                             hipStream_t s)
+                             const void *const st[4], double nu, double drive, int fixp, double *partials,
+                             int64_t *nblocks, hipStream_t s)
 {
     const int64_t n = (int64_t)nx * ny * nz;
     const int64_t nb = state_sums_blocks(n);
@@ -1445,11 +1477,11 @@ hipError_t launch_state_sums(Prec prec, int nx, int ny, int nz, int axis, const 
     if (prec == kF64)
         hipLaunchKernelGGL(k_state_sums<double>, dim3((unsigned)nb), dim3(kSumsBlock), 0, s, nx, ny, nz, axis,
                            codes, (const double *)st[0], (const double *)st[1], (const double *)st[2],
-                           (const double *)st[3], nu, drive, partials);
+                           (const double *)st[3], nu, drive, fixp, partials);
     else
         hipLaunchKernelGGL(k_state_sums<float>, dim3((unsigned)nb), dim3(kSumsBlock), 0, s, nx, ny, nz, axis,
                            codes, (const float *)st[0], (const float *)st[1], (const float *)st[2],
-                           (const float *)st[3], (float)nu, (float)drive, partials);
+                           (const float *)st[3], (float)nu, (float)drive, fixp, partials);
     return hipGetLastError();
 }
 
