@@ -172,6 +172,9 @@ def two_step_measure(ctx, mask_np, mask, args) -> dict:
                      "single_step_same_grid": {"avg_launch_us": round(us1, 2),
                                                "gvox_per_s": round(N / (us1 * 1e-6) / 1e9, 2)},
                      "speedup_vs_single_step": round(2 * us1 / us2, 3)}
+        tr = measured_traffic(form + "_two_step")
+        res[form]["traffic_bytes_per_launch"] = tr
+        res[form]["traffic_bytes_per_voxel_update"] = round(tr / (2 * N), 2) if tr else None
         log(f"[bench] two-step {form}: {us2:.1f} us per launch, {eff:.1f} GVox/s effective "
             f"(single step {N / us1 / 1e3:.1f}), {100 * achieved / HBM_PEAK_GBS:.1f}% HBM per pass")
         del f
