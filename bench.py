@@ -38,7 +38,7 @@ BYTES_PER_VOXEL = {"fp64": 64.375, "fp32": 32.375}
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_fused_spheres256.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_19868_amd", "csrc", f) for f in ("kernels.hip", "common.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_19868_amd", "csrc", f) for f in ("kernels.hip", "common.h", "codes.h")]
 
 
 def log(*a):

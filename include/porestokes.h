@@ -234,10 +234,10 @@ pm_status pm_iterate(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx,
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): pm_iterate
  * without any allocation.  Same arguments, checks and results as pm_iterate
- * (bitwise), for grids whose stencil codes (4 B per voxel) and second field
- * set (4 values per voxel in the call's precision) fit, with a 1 KiB table,
- * in PM_STATIC_SCRATCH_BYTES: up to about 1.86 M voxels in PM_FP64 (123^3) and
- * 3.35 M in PM_FP32 (149^3).  Larger grids are rejected with PM_ERR_ARG before
+ * (bitwise), for grids whose packed stencil codes (2 B per voxel) and second
+ * field set (4 values per voxel in the call's precision) fit, with a 1 KiB
+ * table, in PM_STATIC_SCRATCH_BYTES: up to about 1.97 M voxels in PM_FP64
+ * (125^3) and 3.72 M in PM_FP32 (155^3).  Larger grids are rejected with PM_ERR_ARG before
  * any device work.  The scratch is one static device array per GPU, held from
  * the moment the library is loaded on that GPU until the process ends, and
  * shared by every call on it: calls on one GPU whose sweeps overlap in time

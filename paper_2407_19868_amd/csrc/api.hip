@@ -443,7 +443,7 @@ struct Inst {
     void *user[4] = {nullptr, nullptr, nullptr, nullptr};
     pm_history *hist = nullptr;
     // derived
-    uint32_t *codes = nullptr;
+    uint16_t *codes = nullptr;  // packed stencil codes
     int64_t nflow = 0, nsolid = 0;
     bool no_through_flow = false;  // outer walls close the load axis
     // state
@@ -623,9 +623,9 @@ struct Engine {
                 first_of[in.mask] = i;
             }
             void *p = nullptr;
-            PM_TRY(scratch.get((size_t)in.N * sizeof(uint32_t), &p));
-            in.codes = (uint32_t *)p;
-            PM_HIP(launch_face_codes(in.mask, in.nx, in.ny, in.nz, in.codes, stream));
+            PM_TRY(scratch.get((size_t)in.N * sizeof(uint16_t), &p));
+            in.codes = (uint16_t *)p;
+            PM_HIP(launch_face_codes16(in.mask, in.nx, in.ny, in.nz, in.codes, stream));
         }
         void *dcount = nullptr;
         PM_TRY(scratch.get(4 * sizeof(unsigned long long) * inst.size(), &dcount));
@@ -1215,10 +1215,10 @@ pm_status autotune_shape(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx
     const int64_t N = (int64_t)nx * ny * nz;
     Scratch scratch(ctx);
     void *codes = nullptr, *fields = nullptr, *tab = nullptr, *part = nullptr;
-    PM_TRY(scratch.get((size_t)N * sizeof(uint32_t), &codes));
+    PM_TRY(scratch.get((size_t)N * sizeof(uint16_t), &codes));
     PM_TRY(scratch.get(8 * (size_t)N * elem(prec), &fields));
     PM_TRY(scratch.get(3 * sizeof(InstDev), &tab));
-    PM_HIP(launch_face_codes(mask, nx, ny, nz, (uint32_t *)codes, s));
+    PM_HIP(launch_face_codes16(mask, nx, ny, nz, (uint16_t *)codes, s));
     PM_HIP(hipMemsetAsync(fields, 0, 4 * (size_t)N * elem(prec), s));
     const int tiles[5][2] = {{128, 8}, {64, 8}, {32, 8}, {32, 16}, {64, 16}};
     const int tiles2[6][2] = {{64, 10}, {64, 8}, {64, 6}, {32, 24}, {32, 12}, {32, 8}};
@@ -1283,7 +1283,7 @@ pm_status autotune_shape(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx
         in.ny = ny;
         in.nz = nz;
         in.N = N;
-        in.codes = (uint32_t *)codes;
+        in.codes = (uint16_t *)codes;
         in.prec = prec;
         for (int f = 0; f < 4; ++f) {
             in.set[0][f] = (char *)fields + (size_t)f * N * elem(prec);
@@ -1541,7 +1541,7 @@ pm_status pore_flow(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx, int
 namespace {
 
 // The sweeps of pm_iterate on buffers the caller of this routine provides:
-// codes (N uint32), second (4 N values of the precision), tab (2 InstDev).
+// codes (N packed uint16), second (4 N values of the precision), tab (2 InstDev).
 // timed: record HIP events around the sweeps into ctx->stats.  Every buffer
 // is written before it is read: the codes by the preprocessing kernel, the
 // second set by the first sweep launch, the table by its store kernel.
@@ -1551,8 +1551,8 @@ pm_status iterate_on(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx, in
 {
     const Prec prec = params->precision == PM_FP64 ? kF64 : kF32;
     const int64_t N = (int64_t)nx * ny * nz;
-    PM_HIP(launch_face_codes(mask, nx, ny, nz, (uint32_t *)codes, s));
-    PM_HIP(launch_zero_solid(prec, (const uint32_t *)codes, N, f[0], f[1], f[2], s));
+    PM_HIP(launch_face_codes16(mask, nx, ny, nz, (uint16_t *)codes, s));
+    PM_HIP(launch_zero_solid(prec, (const uint16_t *)codes, N, f[0], f[1], f[2], s));
     void *set[2][4];
     for (int k = 0; k < 4; ++k) {
         set[0][k] = f[k];
@@ -1563,7 +1563,7 @@ pm_status iterate_on(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx, in
         if (timed) PM_TRY(stats_mark(ctx, s, true));
         for (int64_t n = 0; n < count; ++n) {
             const int a = (int)(n & 1);
-            PM_HIP(launch_simple_sweep(prec, nx, ny, nz, axis, (const uint32_t *)codes, set[a], set[a ^ 1], nu,
+            PM_HIP(launch_simple_sweep(prec, nx, ny, nz, axis, (const uint16_t *)codes, set[a], set[a ^ 1], nu,
                                        params->dt, c2dt, params->drive, params->fixed_pressure, s));
         }
         if (timed) PM_TRY(stats_mark(ctx, s, false, 2 * count, count * N));
@@ -1583,7 +1583,7 @@ pm_status iterate_on(pm_ctx *ctx, hipStream_t s, const uint8_t *mask, int nx, in
     in.nz = nz;
     in.axis = axis;
     in.N = N;
-    in.codes = (uint32_t *)codes;
+    in.codes = (uint16_t *)codes;
     in.prec = prec;
     for (int k = 0; k < 4; ++k) {
         in.set[0][k] = set[0][k];
@@ -1695,7 +1695,7 @@ constexpr size_t kStaticTab = 1024;
 static_assert(4 * sizeof(InstDev) <= kStaticTab, "instance table region too small");
 size_t static_bytes_needed(int64_t N, size_t e)
 {
-    const size_t codes = ((size_t)N * 4 + 255) / 256 * 256;
+    const size_t codes = ((size_t)N * 2 + 255) / 256 * 256;
     return kStaticTab + codes + 4 * (size_t)N * e;
 }
 
@@ -1867,7 +1867,7 @@ pm_status pm_iterate(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx,
     const int64_t N = nx * ny * nz;
     Scratch scratch(ctx);
     void *codes = nullptr, *second = nullptr, *tab = nullptr;
-    PM_TRY(scratch.get((size_t)N * 4, &codes));
+    PM_TRY(scratch.get((size_t)N * 2, &codes));
     PM_TRY(scratch.get(4 * (size_t)N * elem(prec), &second));
     PM_TRY(scratch.get(3 * sizeof(InstDev), &tab));
     PM_TRY(iterate_on(ctx, s, mask, (int)nx, (int)ny, (int)nz, axis, params, f, count, codes, second,
@@ -1901,7 +1901,7 @@ pm_status pm_iterate_static(pm_ctx *ctx, void *stream, const uint8_t *mask, int6
     if (count == 0) return PM_OK;
     InstDev *tab = (InstDev *)base;
     void *codes = base + kStaticTab;
-    void *second = base + kStaticTab + ((size_t)N * 4 + 255) / 256 * 256;
+    void *second = base + kStaticTab + ((size_t)N * 2 + 255) / 256 * 256;
     PM_TRY(iterate_on(ctx, (hipStream_t)stream, mask, (int)nx, (int)ny, (int)nz, axis, params, f, count, codes,
                       second, tab, false));
     PM_HIP(hipStreamSynchronize((hipStream_t)stream));
@@ -1926,13 +1926,13 @@ pm_status pm_residual(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx
     const int64_t N = nx * ny * nz;
     Scratch scratch(ctx);
     void *codes = nullptr, *part = nullptr, *refs = nullptr, *sums = nullptr;
-    PM_TRY(scratch.get((size_t)N * 4, &codes));
+    PM_TRY(scratch.get((size_t)N * 2, &codes));
     PM_TRY(scratch.get((size_t)state_sums_blocks(N) * kNumSums * sizeof(double), &part));
     PM_TRY(scratch.get(sizeof(PartialRef), &refs));
     PM_TRY(scratch.get(kNumSums * sizeof(double), &sums));
-    PM_HIP(launch_face_codes(mask, (int)nx, (int)ny, (int)nz, (uint32_t *)codes, s));
+    PM_HIP(launch_face_codes16(mask, (int)nx, (int)ny, (int)nz, (uint16_t *)codes, s));
     int64_t nb = 0;
-    PM_HIP(launch_state_sums(prec, (int)nx, (int)ny, (int)nz, axis, (const uint32_t *)codes, f, 1.0 / params->re,
+    PM_HIP(launch_state_sums(prec, (int)nx, (int)ny, (int)nz, axis, (const uint16_t *)codes, f, 1.0 / params->re,
                              params->drive, params->fixed_pressure, (double *)part, &nb, s));
     PartialRef r{(const double *)part, nb};
     PM_HIP(hipMemcpyAsync(refs, &r, sizeof r, hipMemcpyHostToDevice, s));
@@ -2184,7 +2184,7 @@ pm_status pm_tensor(pm_ctx *ctx, void *stream, const uint8_t *mask, int64_t nx, 
         // stencil codes once, per load case caller-set and internal set (and the
         // correction form's defect field), rounded up for padding by outer walls
         const size_t per_case = 8 * (size_t)N * ue + (params->precision == PM_FP32_DC ? 16 * (size_t)N : 0);
-        const size_t need = (size_t)(1.02 * (double)(4 * (size_t)N + 3 * per_case));
+        const size_t need = (size_t)(1.02 * (double)(2 * (size_t)N + 3 * per_case));
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
             (void)hipGetLastError();

@@ -9,22 +9,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-namespace ps {
+#include "codes.h"
 
-// ---------------------------------------------------------------- face codes
-//
-// Per cell a uint32 holds, for component k at bit offset 8k:
-//   bits 0-2  stencil code along the first perpendicular axis
-//   bits 3-5  stencil code along the second perpendicular axis
-//   bit  6    face solid
-// Perpendicular axes in order: u -> (y, z), v -> (x, z), w -> (x, y).
-// A 3-bit stencil code is L | R << 1 | F << 2 (App. B neighbourhood cases):
-//   L, R  the same-component face at offset -1 / +1 is solid: a wall half a
-//         voxel away (§4, no-slip at voxel faces);
-//   F     only one of L, R is set and the face two steps away on the open
-//         side is solid: a second wall 3/2 voxels away.
-constexpr int kCodeBits = 8;
-constexpr uint32_t kSolidBit = 1u << 6;
+namespace ps {
 
 // Second derivative across the flow from a stencil code:
 //   d2 = a (v[-1] + v[+1]) + b v[0] + gp v[+2] + gm v[-2].

@@ -15,7 +15,7 @@ struct InstDev {
     int32_t nx, ny, nz, axis;
     int32_t tiles_x, tiles_y, tiles_z, zc;
     int64_t blk_begin, nblocks;
-    const uint32_t *codes;
+    const uint16_t *codes;  // packed stencil codes (pack_code)
     void *vel[2][3];     // velocity sets; sweep n reads set (n & 1), writes the other
     void *pres[2];       // pressure sets; sweep n reads p^{n-1} from (n & 1), writes p^n
     double *partials;    // kNumSums doubles per block (written when reducing)
@@ -45,11 +45,14 @@ hipError_t launch_face_bits(const uint8_t *mask, int nx, int ny, int nz, uint32_
                             hipStream_t s);
 hipError_t launch_face_codes(const uint8_t *mask, int nx, int ny, int nz, uint32_t *codes,
                              hipStream_t s);
+// the same codes packed to 16 bits (pack_code), the form the solver reads
+hipError_t launch_face_codes16(const uint8_t *mask, int nx, int ny, int nz, uint16_t *codes,
+                               hipStream_t s);
 // counts (device, 4 x uint64, zeroed by the launcher): solid voxels, fluid x/y/z faces
-hipError_t launch_counts(const uint8_t *mask, const uint32_t *codes, int64_t n,
+hipError_t launch_counts(const uint8_t *mask, const uint16_t *codes, int64_t n,
                          unsigned long long *counts, hipStream_t s);
 // set faces flagged solid in codes to zero
-hipError_t launch_zero_solid(Prec prec, const uint32_t *codes, int64_t n, void *u, void *v, void *w,
+hipError_t launch_zero_solid(Prec prec, const uint16_t *codes, int64_t n, void *u, void *v, void *w,
                              hipStream_t s);
 // outer walls: mask padded with solid layers to (px, py, pz) >= (nx, ny, nz); fields
 // embedded into the padded grid (zero in the added layers) or extracted back
@@ -96,13 +99,13 @@ hipError_t launch_reduce_partials(const PartialRef *refs, int ninst, double *out
 
 // Two-pass reference sweep (velocity, then pressure), one thread per cell;
 // fixp: p~ held on the cell layer x_axis = 0.
-hipError_t launch_simple_sweep(Prec prec, int nx, int ny, int nz, int axis, const uint32_t *codes,
+hipError_t launch_simple_sweep(Prec prec, int nx, int ny, int nz, int axis, const uint16_t *codes,
                                const void *const in[4], void *const out[4], double nu, double dt,
                                double c2dt, double drive, int fixp, hipStream_t s);
 
 // Residual sums of a state into partials (one row of kNumSums per block);
 // returns the number of blocks used through *nblocks.
-hipError_t launch_state_sums(Prec prec, int nx, int ny, int nz, int axis, const uint32_t *codes,
+hipError_t launch_state_sums(Prec prec, int nx, int ny, int nz, int axis, const uint16_t *codes,
                              const void *const st[4], double nu, double drive, int fixp, double *partials,
                              int64_t *nblocks, hipStream_t s);
 int64_t state_sums_blocks(int64_t n);

@@ -65,15 +65,8 @@ __device__ __forceinline__ uint32_t make_code(bool sm2, bool sm1, bool sp1, bool
     return (uint32_t)sm1 | ((uint32_t)sp1 << 1) | ((uint32_t)far << 2);
 }
 
-__global__ void k_face_codes(const uint8_t *__restrict__ mask, int nx, int ny, int nz,
-                             uint32_t *__restrict__ codes)
+__device__ uint32_t face_code(const uint8_t *__restrict__ mask, int nx, int ny, int nz, int x, int y, int z)
 {
-    const int64_t n = (int64_t)nx * ny * nz;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const int x = (int)(t % nx);
-    const int y = (int)((t / nx) % ny);
-    const int z = (int)(t / ((int64_t)nx * ny));
     uint32_t word = 0;
     for (int k = 0; k < 3; ++k) {
         // perpendicular axes in order: u -> (y, z), v -> (x, z), w -> (x, y)
@@ -94,10 +87,34 @@ __global__ void k_face_codes(const uint8_t *__restrict__ mask, int nx, int ny, i
         if (face_solid(mask, nx, ny, nz, k, x, y, z)) c |= kSolidBit;
         word |= c << (kCodeBits * k);
     }
-    codes[t] = word;
+    return word;
 }
 
-__global__ void k_counts(const uint8_t *__restrict__ mask, const uint32_t *__restrict__ codes, int64_t n,
+__global__ void k_face_codes(const uint8_t *__restrict__ mask, int nx, int ny, int nz,
+                             uint32_t *__restrict__ codes)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int x = (int)(t % nx);
+    const int y = (int)((t / nx) % ny);
+    const int z = (int)(t / ((int64_t)nx * ny));
+    codes[t] = face_code(mask, nx, ny, nz, x, y, z);
+}
+
+__global__ void k_face_codes16(const uint8_t *__restrict__ mask, int nx, int ny, int nz,
+                               uint16_t *__restrict__ codes)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int x = (int)(t % nx);
+    const int y = (int)((t / nx) % ny);
+    const int z = (int)(t / ((int64_t)nx * ny));
+    codes[t] = pack_code(face_code(mask, nx, ny, nz, x, y, z));
+}
+
+__global__ void k_counts(const uint8_t *__restrict__ mask, const uint16_t *__restrict__ codes, int64_t n,
                          unsigned long long *__restrict__ counts)
 {
     __shared__ unsigned long long sc[4];
@@ -107,7 +124,7 @@ __global__ void k_counts(const uint8_t *__restrict__ mask, const uint32_t *__res
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x) {
         c[0] += mask[t] != 0;
-        const uint32_t w = codes[t];
+        const uint32_t w = unpack_code(codes[t]);
         for (int k = 0; k < 3; ++k) c[1 + k] += ((w >> (kCodeBits * k)) & kSolidBit) == 0;
     }
     for (int i = 0; i < 4; ++i) atomicAdd(&sc[i], c[i]);
@@ -116,12 +133,12 @@ __global__ void k_counts(const uint8_t *__restrict__ mask, const uint32_t *__res
 }
 
 template <typename T>
-__global__ void k_zero_solid(const uint32_t *__restrict__ codes, int64_t n, T *__restrict__ u,
+__global__ void k_zero_solid(const uint16_t *__restrict__ codes, int64_t n, T *__restrict__ u,
                              T *__restrict__ v, T *__restrict__ w)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    const uint32_t c = codes[t];
+    const uint32_t c = unpack_code(codes[t]);
     if (c & kSolidBit) u[t] = T(0);
     if ((c >> kCodeBits) & kSolidBit) v[t] = T(0);
     if ((c >> (2 * kCodeBits)) & kSolidBit) w[t] = T(0);
@@ -186,7 +203,14 @@ hipError_t launch_face_codes(const uint8_t *mask, int nx, int ny, int nz, uint32
     return hipGetLastError();
 }
 
-hipError_t launch_counts(const uint8_t *mask, const uint32_t *codes, int64_t n, unsigned long long *counts,
+hipError_t launch_face_codes16(const uint8_t *mask, int nx, int ny, int nz, uint16_t *codes, hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    hipLaunchKernelGGL(k_face_codes16, dim3(grid1d(n, 256)), dim3(256), 0, s, mask, nx, ny, nz, codes);
+    return hipGetLastError();
+}
+
+hipError_t launch_counts(const uint8_t *mask, const uint16_t *codes, int64_t n, unsigned long long *counts,
                          hipStream_t s)
 {
     hipError_t e = hipMemsetAsync(counts, 0, 4 * sizeof(unsigned long long), s);
@@ -197,7 +221,7 @@ hipError_t launch_counts(const uint8_t *mask, const uint32_t *codes, int64_t n, 
     return hipGetLastError();
 }
 
-hipError_t launch_zero_solid(Prec prec, const uint32_t *codes, int64_t n, void *u, void *v, void *w,
+hipError_t launch_zero_solid(Prec prec, const uint16_t *codes, int64_t n, void *u, void *v, void *w,
                              hipStream_t s)
 {
     if (prec == kF64)
@@ -385,6 +409,27 @@ __device__ __forceinline__ void fill_coef4(Coef4<T> *tab, int tid)
     }
 }
 
+// Packed codes in the sweeps: per component a 37-entry table in LDS gives the
+// component's field of the 32-bit form, already shifted into place; unpacking
+// is two divisions by constants and three table reads.  (A table indexed by
+// i_u + 37 i_v would save one read but costs a short z-chunk more to fill
+// than to sweep.)
+constexpr int kCodeLut = 3 * (int)kPackBase;
+
+__device__ __forceinline__ void fill_code_lut(uint32_t *lut, int tid)
+{
+    if (tid < kCodeLut) {
+        const uint32_t k = (uint32_t)tid / kPackBase, i = (uint32_t)tid - k * kPackBase;
+        lut[tid] = unpack_component(i) << (kCodeBits * k);
+    }
+}
+
+__device__ __forceinline__ uint32_t lut_code(const uint32_t *lut, uint32_t p)
+{
+    const uint32_t iw = p / kPackUV, r = p - iw * kPackUV, iv = r / kPackBase, iu = r - iv * kPackBase;
+    return (lut[iu] | lut[kPackBase + iv]) | lut[2 * kPackBase + iw];
+}
+
 template <bool B>
 struct BoolC {
     static constexpr bool value = B;
@@ -413,7 +458,9 @@ __device__ __forceinline__ Rsrc rsrc_at(const void *base, int64_t off_b, uint32_
 template <typename T, int AUX = 0>
 __device__ __forceinline__ T bload(Rsrc r, uint32_t off)
 {
-    if constexpr (sizeof(T) == 8)
+    if constexpr (sizeof(T) == 2)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, AUX));
+    else if constexpr (sizeof(T) == 8)
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
     else
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
@@ -462,6 +509,7 @@ struct FusedShared {
     T p[2][PP];
     T w[3][PP];
     Coef4<T> tab[8];
+    uint32_t lut[kCodeLut];
     double red[kNumSums * (TX * TY / 64)];
 };
 
@@ -543,7 +591,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
     const int z1 = min(z0 + I.zc, nz);
     const int64_t plane = (int64_t)nx * ny;
     const int64_t plane_b = plane * (int64_t)sizeof(T), field_b = plane_b * nz;  // fields
-    const int64_t plane_c = plane * 4, field_c = plane_c * nz;                   // codes
+    const int64_t plane_c = plane * 2, field_c = plane_c * nz;                   // codes
     const int eff = parity ^ I.par_off;
     const T *const Uin = (const T *)I.vel[eff][0];
     const T *const Vin = (const T *)I.vel[eff][1];
@@ -553,7 +601,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
     T *const Vout = (T *)I.vel[eff ^ 1][1];
     T *const Wout = (T *)I.vel[eff ^ 1][2];
     T *const Pout = (T *)I.pres[eff ^ 1];
-    const uint32_t *const codes = I.codes;
+    const uint16_t *const codes = I.codes;
     const T *const Su = (const T *)I.src[0];
     const T *const Sv = (const T *)I.src[1];
     const T *const Sw = (const T *)I.src[2];
@@ -567,13 +615,14 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     fill_coef4(sh.tab, tid);
+    fill_code_lut(sh.lut, tid);
 
     // ---- own column (inactive threads hold the wrapped column: LDS stays periodic)
     const int gx = x0 + tx, gy = y0 + ty;
     const bool active = gx < nx && gy < ny;
     const int own = wrap_int(gy, ny) * nx + wrap_int(gx, nx);
     const HeldLayer held(I, gx, gy);
-    const uint32_t own_b = (uint32_t)own * (uint32_t)sizeof(T), own_c = (uint32_t)own * 4u;
+    const uint32_t own_b = (uint32_t)own * (uint32_t)sizeof(T), own_c = (uint32_t)own * 2u;
     const int cl = (ty + 2) * PX + (tx + 2);  // own position in the padded plane
 
     // ---- halo position of this thread in the padded plane (ring of width 2)
@@ -679,7 +728,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
             bV = bload<T>(rsrc_at(Vin, zb3, plane_b), own_b);
             bW = bload<T>(rW2, own_b);
             bP = bload<T>(rP1, own_b);
-            bC = bload<uint32_t, kNonTemporal>(rsrc_at(codes, zc1, plane_c), own_c);
+            bC = bload<uint16_t, kNonTemporal>(rsrc_at(codes, zc1, plane_c), own_c);
         }
         T bhU = T(0), bhV = T(0), bhW = T(0), bhP = T(0);
         if (has_halo && ahead) {
@@ -705,7 +754,8 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
             const T pym = (skip || held.ym || hz) ? sp[cl - PX] : fma(-c2dt, dym, sp[cl - PX]);
             bstore<T, kNonTemporal>(SRC ? pn + sP : pn, rsrc_at(Pout, zb0, plane_b), own_b);
             // u: own axis x, across y (LDS) and z (registers)
-            const uint32_t cu = code;
+            const uint32_t word = lut_code(sh.lut, code);
+            const uint32_t cu = word;
             const T u0 = Uw[2];
             const T u_d2x = d2_own(su[cl - 1], u0, su[cl + 1]);
             const T u_d2y = d2_perp_t4(sh.tab, cu & 7, su[cl - 2 * PX], su[cl - PX], u0, su[cl + PX], su[cl + 2 * PX]);
@@ -715,7 +765,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
             bstore<T, kNonTemporal>(su_ ? T(0) : (SRC ? fma(dt, Fu, u0) + sU : fma(dt, Fu, u0)),
                                     rsrc_at(Uout, zb0, plane_b), own_b);
             // v: own axis y, across x (LDS) and z (registers)
-            const uint32_t cv = code >> kCodeBits;
+            const uint32_t cv = word >> kCodeBits;
             const T v0 = Vw[2];
             const T v_d2x = d2_perp_t4(sh.tab, cv & 7, sv[cl - 2], sv[cl - 1], v0, sv[cl + 1], sv[cl + 2]);
             const T v_d2y = d2_own(sv[cl - PX], v0, sv[cl + PX]);
@@ -725,7 +775,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
             bstore<T, kNonTemporal>(sv_ ? T(0) : (SRC ? fma(dt, Fv, v0) + sV : fma(dt, Fv, v0)),
                                     rsrc_at(Vout, zb0, plane_b), own_b);
             // w: own axis z (registers), across x and y (LDS)
-            const uint32_t cw = code >> (2 * kCodeBits);
+            const uint32_t cw = word >> (2 * kCodeBits);
             const T w0 = Ww[1];
             const T w_d2x = d2_perp_t4(sh.tab, cw & 7, swc[cl - 2], swc[cl - 1], w0, swc[cl + 1], swc[cl + 2]);
             const T w_d2y = d2_perp_t4(sh.tab, (cw >> 3) & 7, swc[cl - 2 * PX], swc[cl - PX], w0, swc[cl + PX],
@@ -836,6 +886,7 @@ struct Fused2Shared {
     T p2[NT];
     T w2[2][NT];
     Coef4<T> tab[8];
+    uint32_t lut[kCodeLut];
 };
 
 template <typename T, int OX, int OY>
@@ -880,7 +931,7 @@ k_fused2(const InstDev *__restrict__ insts, int ninst, int parity)
     const int zend = min(z0 + I.zc, nz);
     const int64_t plane = (int64_t)nx * ny;
     const int64_t plane_b = plane * (int64_t)sizeof(T), field_b = plane_b * nz;
-    const int64_t plane_c = plane * 4, field_c = plane_c * nz;
+    const int64_t plane_c = plane * 2, field_c = plane_c * nz;
     const int eff = parity ^ I.par_off;
     const T *const Uin = (const T *)I.vel[eff][0];
     const T *const Vin = (const T *)I.vel[eff][1];
@@ -890,7 +941,7 @@ k_fused2(const InstDev *__restrict__ insts, int ninst, int parity)
     T *const Vout = (T *)I.vel[eff ^ 1][1];
     T *const Wout = (T *)I.vel[eff ^ 1][2];
     T *const Pout = (T *)I.pres[eff ^ 1];
-    const uint32_t *const codes = I.codes;
+    const uint16_t *const codes = I.codes;
     const T nu = (T)I.nu, dt = (T)I.dt, c2dt = (T)I.c2dt;
     const T gu = I.axis == 0 ? (T)I.drive : T(0);
     const T gv = I.axis == 1 ? (T)I.drive : T(0);
@@ -899,12 +950,13 @@ k_fused2(const InstDev *__restrict__ insts, int ninst, int parity)
     const int tid = threadIdx.x;
     const int tx = tid % SX, ty = tid / SX;
     fill_coef4(sh.tab, tid);
+    fill_code_lut(sh.lut, tid);
 
     // ---- own column (wrapped: the region may reach across the periodic boundary)
     const bool is_out = tx >= 2 && tx < SX - 2 && ty >= 2 && ty < SY - 2;
     const int own = wrap_int(Y1 + ty, ny) * nx + wrap_int(X1 + tx, nx);
     const HeldLayer held(I, X1 + tx, Y1 + ty);
-    const uint32_t own_b = (uint32_t)own * (uint32_t)sizeof(T), own_c = (uint32_t)own * 4u;
+    const uint32_t own_b = (uint32_t)own * (uint32_t)sizeof(T), own_c = (uint32_t)own * 2u;
     // stores: output lanes at their column (lanes of a column beyond the grid
     // store the identical values of the wrapped column); ring lanes beyond the
     // plane, where the store is dropped, so that every step stores
@@ -1012,7 +1064,7 @@ k_fused2(const InstDev *__restrict__ insts, int ninst, int parity)
             bV = bload<T>(rsrc_at(Vin, zb3, plane_b), own_b);
             bW = bload<T>(rW2, own_b);
             bP = bload<T>(rP1, own_b);
-            bC = bload<uint32_t, kNonTemporal>(rsrc_at(codes, zc1, plane_c), own_c);
+            bC = bload<uint16_t, kNonTemporal>(rsrc_at(codes, zc1, plane_c), own_c);
         }
         T bhU = T(0), bhV = T(0), bhW = T(0), bhP = T(0);
         if (has_halo && ahead) {
@@ -1031,21 +1083,22 @@ k_fused2(const InstDev *__restrict__ insts, int ninst, int parity)
             const T pxm = (held.xm || hz) ? sp[cl - 1] : fma(-c2dt, dxm, sp[cl - 1]);
             const T dym = divergence(su[cl - PX], su[cl - PX + 1], sv[cl - PX], Vw[2], swc[cl - PX], swn[cl - PX]);
             const T pym = (held.ym || hz) ? sp[cl - PX] : fma(-c2dt, dym, sp[cl - PX]);
-            const uint32_t cu = code;
+            const uint32_t word = lut_code(sh.lut, code);
+            const uint32_t cu = word;
             const T u0 = Uw[2];
             const T u_d2x = d2_own(su[cl - 1], u0, su[cl + 1]);
             const T u_d2y = d2_perp_t4(sh.tab, cu & 7, su[cl - 2 * PX], su[cl - PX], u0, su[cl + PX], su[cl + 2 * PX]);
             const T u_d2z = d2_perp_t4(sh.tab, (cu >> 3) & 7, Uw[0], Uw[1], u0, Uw[3], Uw[4]);
             const T Fu = momentum(u_d2x, u_d2y, u_d2z, pn, pxm, nu, gu);
             const T u1 = (cu & kSolidBit) != 0 ? T(0) : fma(dt, Fu, u0);
-            const uint32_t cv = code >> kCodeBits;
+            const uint32_t cv = word >> kCodeBits;
             const T v0 = Vw[2];
             const T v_d2x = d2_perp_t4(sh.tab, cv & 7, sv[cl - 2], sv[cl - 1], v0, sv[cl + 1], sv[cl + 2]);
             const T v_d2y = d2_own(sv[cl - PX], v0, sv[cl + PX]);
             const T v_d2z = d2_perp_t4(sh.tab, (cv >> 3) & 7, Vw[0], Vw[1], v0, Vw[3], Vw[4]);
             const T Fv = momentum(v_d2x, v_d2y, v_d2z, pn, pym, nu, gv);
             const T v1 = (cv & kSolidBit) != 0 ? T(0) : fma(dt, Fv, v0);
-            const uint32_t cw = code >> (2 * kCodeBits);
+            const uint32_t cw = word >> (2 * kCodeBits);
             const T w0 = Ww[1];
             const T w_d2x = d2_perp_t4(sh.tab, cw & 7, swc[cl - 2], swc[cl - 1], w0, swc[cl + 1], swc[cl + 2]);
             const T w_d2y = d2_perp_t4(sh.tab, (cw >> 3) & 7, swc[cl - 2 * PX], swc[cl - PX], w0, swc[cl + PX],
@@ -1069,7 +1122,7 @@ k_fused2(const InstDev *__restrict__ insts, int ninst, int parity)
             P1[2] = pn;
             C1[0] = C1[1];
             C1[1] = C1[2];
-            C1[2] = code;
+            C1[2] = word;
         }
         if constexpr (stage1_only) __syncthreads();
 
@@ -1314,7 +1367,7 @@ __device__ __forceinline__ T ld(const T *__restrict__ f, int nx, int ny, int nz,
 }
 
 template <typename T>
-__global__ void k_simple_vel(int nx, int ny, int nz, int axis, const uint32_t *__restrict__ codes,
+__global__ void k_simple_vel(int nx, int ny, int nz, int axis, const uint16_t *__restrict__ codes,
                              const T *__restrict__ U, const T *__restrict__ V, const T *__restrict__ W,
                              const T *__restrict__ P, T *__restrict__ Uo, T *__restrict__ Vo, T *__restrict__ Wo,
                              T nu, T dt, T drive)
@@ -1323,7 +1376,7 @@ __global__ void k_simple_vel(int nx, int ny, int nz, int axis, const uint32_t *_
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int x = (int)(t % nx), y = (int)((t / nx) % ny), z = (int)(t / ((int64_t)nx * ny));
-    const uint32_t code = codes[t];
+    const uint32_t code = unpack_code(codes[t]);
     const T pc = P[t];
     {
         const uint32_t c = code;
@@ -1379,7 +1432,7 @@ __global__ void k_simple_pres(int nx, int ny, int nz, int axis, int fixp, const 
 }
 
 template <typename T>
-static hipError_t simple_sweep_t(int nx, int ny, int nz, int axis, const uint32_t *codes, const void *const in[4],
+static hipError_t simple_sweep_t(int nx, int ny, int nz, int axis, const uint16_t *codes, const void *const in[4],
                                  void *const out[4], double nu, double dt, double c2dt, double drive, int fixp,
                                  hipStream_t s)
 {
@@ -1395,7 +1448,7 @@ static hipError_t simple_sweep_t(int nx, int ny, int nz, int axis, const uint32_
     return hipGetLastError();
 }
 
-hipError_t launch_simple_sweep(Prec prec, int nx, int ny, int nz, int axis, const uint32_t *codes,
+hipError_t launch_simple_sweep(Prec prec, int nx, int ny, int nz, int axis, const uint16_t *codes,
                                const void *const in[4], void *const out[4], double nu, double dt, double c2dt,
                                double drive, int fixp, hipStream_t s)
 {
@@ -1418,7 +1471,7 @@ int64_t state_sums_blocks(int64_t n)
 }
 
 template <typename T>
-__global__ void k_state_sums(int nx, int ny, int nz, int axis, const uint32_t *__restrict__ codes,
+__global__ void k_state_sums(int nx, int ny, int nz, int axis, const uint16_t *__restrict__ codes,
                              const T *__restrict__ U, const T *__restrict__ V, const T *__restrict__ W,
                              const T *__restrict__ P, T nu, T drive, int fixp, double *__restrict__ partials)
 {
@@ -1427,7 +1480,7 @@ __global__ void k_state_sums(int nx, int ny, int nz, int axis, const uint32_t *_
     double acc[kNumSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(t % nx), y = (int)((t / nx) % ny), z = (int)(t / ((int64_t)nx * ny));
-        const uint32_t code = codes[t];
+        const uint32_t code = unpack_code(codes[t]);
         const T pc = P[t];
         const T* F3[3] = {U, V, W};
         for (int k = 0; k < 3; ++k) {
@@ -1467,7 +1520,7 @@ __global__ void k_state_sums(int nx, int ny, int nz, int axis, const uint32_t *_
     block_sums(acc, scratch, partials + (int64_t)blockIdx.x * kNumSums);
 }
 
-hipError_t launch_state_sums(Prec prec, int nx, int ny, int nz, int axis, const uint32_t *codes,
+hipError_t launch_state_sums(Prec prec, int nx, int ny, int nz, int axis, const uint16_t *codes,
                              const void *const st[4], double nu, double drive, int fixp, double *partials,
                              int64_t *nblocks, hipStream_t s)
 {

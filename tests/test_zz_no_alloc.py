@@ -40,7 +40,7 @@ def test_static_iterate_equals_iterate(prec, kernel, tblock):
 
 def test_static_iterate_rejects_grids_beyond_its_scratch():
     torch.cuda.set_device(0)
-    mask = np.zeros((124, 124, 124), dtype=np.uint8)  # 1.91 M voxels: over the FP64 limit
+    mask = np.zeros((128, 128, 128), dtype=np.uint8)  # 2.10 M voxels: over the FP64 limit (1.97 M)
     mask[:, :, 0] = 1
     m = ps.to_device(mask)
     f = [torch.zeros(mask.shape, dtype=torch.float64, device="cuda") for _ in range(4)]
