@@ -142,9 +142,9 @@ typedef struct {
     int32_t tile2_y;    /* (tile2_x, tile2_y) one of 64x10, 64x8, 64x6, 32x24, 32x12,
                            32x8                                                      */
     int32_t zchunk2;    /* planes per two-sweep workgroup along z (0 = auto)         */
-    int32_t fixed_pressure; /* §4 "in main flow direction we employ fixed pressure
-                           conditions" (Fig. 2: p_in, p_out), with the flux kept
-                           periodic: 1 holds p~ on the cell layer x_axis = 0 at
+    int32_t fixed_pressure; /* §4 (boundary conditions; Fig. 2 p_in, p_out): the
+                           pressure is fixed along the drive while the flux stays
+                           periodic.  1 holds p~ on the cell layer x_axis = 0 at
                            its starting value (0 from rest), so the pressure is
                            p_in there and p_out = p_in - G n one period later;
                            that layer's mass balance is not imposed and its
@@ -363,8 +363,8 @@ typedef struct {
 pm_status pm_last_stats(const pm_ctx *ctx, pm_stats *out);
 
 /*
- * Mirroring (§5.1 pre-processing "mirroring for symmetric periodicity"; the
- * mirrored samples of §7.1): the sample followed by its mirror image along every
+ * Mirroring (§5.1 pre-processing, which mirrors a sample to make it periodic;
+ * the mirrored samples of §7.1): the sample followed by its mirror image along every
  * axis i with bit i of `axes`, so that the periodic cell is continuous across
  * its boundaries.  out: device uint8 [mz][my][mx], m_i = 2 n_i for mirrored axes,
  * n_i otherwise; out at coordinate c >= n_i equals the sample at 2 n_i - 1 - c.

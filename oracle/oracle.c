@@ -24,8 +24,8 @@
  *     parametrization": initial gradient 1/vx, Re = 0.01, c*^2 = 1.5e6);
  *   - Darcy (§4 eq. darcy, App. C): k_{i,axis} = dx^2 q_i / (Re G), q_i the
  *     mean of u_i over all i-faces;
- *   - optional fixed pressure in the main flow direction (§4 "Boundary in the
- *     numerically considered domain", Fig. 2 p_in / p_out): p~ held on the
+ *   - optional fixed pressure in the main flow direction (§4, boundary of the
+ *     numerically considered domain; Fig. 2 p_in / p_out): p~ held on the
  *     cell layer x_axis = 0, so that p = p_in there and p_out = p_in - G n
  *     one period later; that layer's mass balance is not imposed and it is
  *     left out of the residual's divergence sum.
@@ -49,11 +49,11 @@ typedef struct {
     int32_t check_every;
     int32_t warm_start; /* 1: start from the given fields               */
     int32_t stop_rule;  /* 0: residual r, 1: relative flux change eps_q */
-    int32_t fixed_pressure; /* 1: §4 "in main flow direction we employ fixed
-                           pressure conditions", read as: p~ is held at its
-                           value (0 from rest) on the cell layer x_axis = 0,
-                           whose mass balance is not imposed; the velocity
-                           stays periodic ("periodic for the local flux") */
+    int32_t fixed_pressure; /* 1: §4 fixes the pressure along the drive, read
+                           as: p~ is held at its value (0 from rest) on the
+                           cell layer x_axis = 0, whose mass balance is not
+                           imposed; the velocity stays periodic (§4 keeps the
+                           local flux periodic)                             */
 } orc_params;
 
 enum { ORC_OK = 0, ORC_ERR_ARG = 1, ORC_ERR_OOM = 2, ORC_NOT_CONVERGED = 4, ORC_DIVERGED = 5,

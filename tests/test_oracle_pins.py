@@ -433,8 +433,8 @@ def test_outer_walls_duct_sylvester(H, W):
 
 # ------------------------------------------------------------ fixed pressure (§4)
 #
-# Reading of §4 "in main flow direction we employ fixed pressure conditions"
-# with a flux that stays periodic: p~ is held on the cell layer x_axis = 0
+# Reading of §4's fixed pressure along the main flow direction, with a flux
+# that stays periodic: p~ is held on the cell layer x_axis = 0
 # (p = p_in there, p_out = p_in - G n one period later) and that layer's mass
 # balance is not imposed.
 
