@@ -150,6 +150,16 @@ typedef struct {
                            that layer's mass balance is not imposed and its
                            cells are left out of the residual's divergence sum.
                            0: p~ periodic and free everywhere.     default 0        */
+    int32_t persistent; /* 1: small instances (both field sets and the codes within
+                           3 MiB) run each block of check_every - 1 sweeps as one
+                           persistent launch, instance j of up to 8 on XCD j, 32x16
+                           tiles, at most 32 workgroups per instance, a barrier in
+                           the XCD's L2 between sweeps (solves, tensors and batches;
+                           results are bitwise the same).  On MI355X it gains where
+                           several small instances run side by side (three 32^3
+                           load cases: 11.0 against 14.1 ms) and loses on a single
+                           FP64 32^3 solve (7.0 against 6.2 us per sweep).  0: one
+                           launch per sweep.                     default 0            */
 } pm_params;
 
 /* Residual history: one record per check.  Host arrays of length cap owned by
@@ -357,6 +367,8 @@ typedef struct {
     int64_t t2_voxels;       /* voxels those launches passed over (each advanced 2 sweeps) */
     double t2_ms;            /* GPU time spanned by the runs of consecutive two-step launches
                                 (HIP events on the call's stream)                         */
+    int64_t pers_launches;   /* persistent launches among sweep_launches (pm_params.persistent) */
+    int64_t pers_sweeps;     /* instance-sweeps done inside them                          */
 } pm_stats;
 
 /* Copy the statistics of the last call into *out (host). */

@@ -62,6 +62,7 @@ class PmParams(ctypes.Structure):
         ("tile2_y", ctypes.c_int32),
         ("zchunk2", ctypes.c_int32),
         ("fixed_pressure", ctypes.c_int32),
+        ("persistent", ctypes.c_int32),
     ]
 
 
@@ -116,6 +117,8 @@ class PmStats(ctypes.Structure):
         ("t2_launches", ctypes.c_int64),
         ("t2_voxels", ctypes.c_int64),
         ("t2_ms", ctypes.c_double),
+        ("pers_launches", ctypes.c_int64),
+        ("pers_sweeps", ctypes.c_int64),
     ]
 
 

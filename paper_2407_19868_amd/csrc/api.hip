@@ -35,6 +35,11 @@ struct pm_ctx {
     bool tune_loaded = false;
     pm_stats stats{};
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // persistent sweeps: barrier counters, the timeout flag, and whether this
+    // device places workgroup i on XCD i mod 8 (-1: not checked yet)
+    unsigned *d_bar = nullptr;
+    int *d_fail = nullptr;
+    int pers_ok = -1;
 };
 
 namespace {
@@ -176,6 +181,29 @@ void stats_begin(pm_ctx *ctx)
 
 void stats_end(pm_ctx *ctx) { ctx->stats.total_ms += now_ms(); }
 
+// Buffers of the persistent sweeps, and the check that the dispatcher places
+// workgroup i on XCD i mod 8 (the XCD of each workgroup of a 64-workgroup
+// launch, from the hardware's XCC id): without it the path stays off.
+pm_status ensure_pers(pm_ctx *ctx, hipStream_t s)
+{
+    if (ctx->pers_ok >= 0) return PM_OK;
+    ctx->pers_ok = 0;
+    PM_HIP(hipMalloc(&ctx->d_bar, kPersXcds * kBarrierStride * sizeof(unsigned)));
+    PM_HIP(hipMalloc(&ctx->d_fail, sizeof(int)));
+    PM_HIP(hipMemsetAsync(ctx->d_fail, 0, sizeof(int), s));
+    static_assert(kXccProbeBlocks <= kPersXcds * kBarrierStride, "probe output must fit the counters");
+    PM_HIP(launch_xcc_ids(ctx->d_bar, s));
+    unsigned ids[kXccProbeBlocks];
+    PM_HIP(hipMemcpyAsync(ids, ctx->d_bar, sizeof ids, hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    bool ok = true;
+    for (int i = 0; i < kXccProbeBlocks; ++i) ok = ok && ids[i] == ids[i % kPersXcds];
+    for (int i = 0; i < kPersXcds; ++i)
+        for (int j = 0; j < i; ++j) ok = ok && ids[i] != ids[j];
+    ctx->pers_ok = ok ? 1 : 0;
+    return PM_OK;
+}
+
 pm_status ensure_events(pm_ctx *ctx)
 {
     for (int i = 0; i < 4; ++i)
@@ -246,6 +274,7 @@ pm_status check_params(pm_ctx *ctx, const pm_params *p)
     if (p->zchunk2 < 0) return fail(ctx, PM_ERR_ARG, "zchunk2 must be >= 0");
     if (p->fixed_pressure != 0 && p->fixed_pressure != 1)
         return fail(ctx, PM_ERR_ARG, "fixed_pressure must be 0 or 1");
+    if (p->persistent != 0 && p->persistent != 1) return fail(ctx, PM_ERR_ARG, "persistent must be 0 or 1");
     return PM_OK;
 }
 
@@ -607,6 +636,7 @@ struct Engine {
     pm_status prepare()
     {
         choose_batch_tiles();
+        if (prm->persistent == 1) PM_TRY(ensure_pers(ctx, stream));
         // stencil codes and counts, once per distinct mask
         std::map<const void *, size_t> first_of;
         for (size_t i = 0; i < inst.size(); ++i) {
@@ -728,6 +758,25 @@ struct Engine {
 
     InstDev dev_of(const Inst &in, int64_t blk_begin, bool skip) const { return make_dev(in, prm, blk_begin, skip); }
 
+    // Whether an instance's blocks of sweeps run as persistent launches, and
+    // its decomposition there: 32x16 tiles (the smallest plane step that
+    // covers a 32-wide grid) with z-chunks long enough that it takes at most
+    // kPersMaxBlocks workgroups (one XCD).  Only where the two field sets and
+    // the codes fit one XCD's L2 (4 MB; 3 MiB taken): beyond that one XCD's
+    // share of HBM bandwidth would cost more than the launches it saves.
+    bool pers_cfg(const Inst &in, int *zc, int64_t *nb) const
+    {
+        if (prm->persistent != 1 || ctx->pers_ok != 1 || in.delta) return false;
+        const size_t ws = 8 * elem(in.prec) * (size_t)in.N + sizeof(uint16_t) * (size_t)in.N;
+        if (ws > kPersL2Bytes) return false;
+        const int64_t tpp = (int64_t)((in.nx + kPersTX - 1) / kPersTX) * ((in.ny + kPersTY - 1) / kPersTY);
+        if (tpp > kPersMaxBlocks) return false;
+        const int64_t chunks = std::min<int64_t>(in.nz, kPersMaxBlocks / tpp);
+        *zc = (int)((in.nz + chunks - 1) / chunks);
+        *nb = tpp * ((in.nz + *zc - 1) / *zc);
+        return true;
+    }
+
     // Advance the selected instances by `steps` sweeps (skip: the one
     // pressure-passthrough step that starts a pipeline) with the residual sums
     // of the last one, and bring the sums to ctx->h_sums in selection order.
@@ -752,6 +801,10 @@ struct Engine {
             int first2;
             int64_t blocks2;
             int n2, n1;  // two-step and single-step launches of the plan
+            bool pers;   // the first steps - 1 sweeps as one persistent launch
+            int firstp;
+            int64_t maxbp;  // most workgroups of one instance in it
+            int np;         // sweeps in it
         };
         std::vector<Group> groups;
         std::vector<int> order;
@@ -760,13 +813,17 @@ struct Engine {
                 const Inst &in = inst[i];
                 if (pass != (in.prec == kF64 ? 2 : in.delta ? 1 : 0)) continue;
                 const bool alone = alone_of(in);
-                const bool two = !skip && steps >= 3 && two_step(in);
+                int pzc = 0;
+                int64_t pnb = 0;
+                const bool pers = !skip && steps >= 2 && pers_cfg(in, &pzc, &pnb);
+                const bool two = !pers && !skip && steps >= 3 && two_step(in);
                 if (groups.empty() || groups.back().prec != in.prec || groups.back().src != in.delta ||
                     groups.back().alone != alone || groups.back().tx != in.tile.tx || groups.back().ty != in.tile.ty ||
                     groups.back().two != two ||
-                    (two && (groups.back().ox != in.tile.ox || groups.back().oy != in.tile.oy)))
+                    (two && (groups.back().ox != in.tile.ox || groups.back().oy != in.tile.oy)) ||
+                    groups.back().pers != pers || (pers && groups.back().count == kPersXcds))
                     groups.push_back({in.prec, in.delta, alone, two, in.tile.tx, in.tile.ty, in.tile.ox, in.tile.oy,
-                                      (int)h_tab.size(), 0, 0, 0, 0, 0, 0});
+                                      (int)h_tab.size(), 0, 0, 0, 0, 0, 0, pers, 0, 0, 0});
                 Group &g = groups.back();
                 h_tab.push_back(dev_of(in, g.blocks, skip));
                 g.blocks += in.nblocks;
@@ -785,6 +842,23 @@ struct Engine {
                     g.blocks2 += in.nblocks2;
                     vox2 += in.N * g.n2;
                 }
+            } else if (g.pers) {
+                // instance k of the group on XCD k, its own decomposition
+                g.np = steps - 1;
+                g.n1 = 1;
+                g.firstp = (int)h_tab.size();
+                int64_t bb = 0;
+                for (int k = 0; k < g.count; ++k) {
+                    Inst ip = inst[order[g.first + k]];
+                    int64_t nb = 0;
+                    pers_cfg(ip, &ip.tile.zc, &nb);
+                    ip.tile.tx = kPersTX;
+                    ip.tile.ty = kPersTY;
+                    ip.nblocks = nb;
+                    h_tab.push_back(make_dev(ip, prm, bb, false));
+                    bb += nb;
+                    g.maxbp = std::max(g.maxbp, nb);
+                }
             } else {
                 g.n1 = steps;
             }
@@ -795,10 +869,14 @@ struct Engine {
                               stream));
         int64_t vox = 0;
         for (int i : order) vox += inst[i].N;
-        int64_t launches = 0, launches2 = 0;
+        int64_t launches = 0, launches2 = 0, launchesp = 0, sweepsp = 0;
         for (const Group &g : groups) {
-            launches += g.n1 + g.n2;
+            launches += g.n1 + g.n2 + (g.pers ? 1 : 0);
             launches2 += g.n2;
+            if (g.pers) {
+                launchesp += 1;
+                sweepsp += (int64_t)g.np * g.count;
+            }
         }
         PM_TRY(ensure_events(ctx));
         // the sequence, in two parts: (a) the two-step launches of every group;
@@ -813,9 +891,12 @@ struct Engine {
             return PM_OK;
         };
         auto enqueue_one = [&](hipStream_t st) -> pm_status {
-            for (const Group &g : groups)
+            for (const Group &g : groups) {
+                if (g.pers)
+                    PM_HIP(launch_fused_pers(g.prec, kPersTX, kPersTY, d_tab + g.firstp, g.count, g.maxbp, 0, g.np,
+                                             ctx->d_bar, ctx->d_fail, st));
                 for (int k = 0; k < g.n1; ++k) {
-                    const int j = g.n2 + k;
+                    const int j = g.n2 + g.np + k;
                     const int red = k == g.n1 - 1 ? 1 : 0;
                     if (g.src)
                         PM_HIP(launch_fused_src(g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1, red, st,
@@ -824,12 +905,13 @@ struct Engine {
                         PM_HIP(launch_fused(g.prec, g.tx, g.ty, d_tab + g.first, g.count, g.blocks, j & 1, red, st,
                                             g.alone));
                 }
+            }
             PM_HIP(launch_reduce_partials(d_refs, (int)order.size(), d_sums, st));
             PM_HIP(hipMemcpyAsync(ctx->h_sums, d_sums, order.size() * kNumSums * sizeof(double),
                                   hipMemcpyDeviceToHost, st));
             return PM_OK;
         };
-        if (prm->graphs && !skip) {
+        if (prm->graphs && !skip && launchesp == 0) {
             std::string key;
             for (const Group &g : groups)
                 key += "|" + std::to_string(g.prec) + (g.src ? "s" : "") + (g.alone ? "a" : "") + ":" +
@@ -868,6 +950,8 @@ struct Engine {
                 ctx->stats.t2_launches += launches2;
                 ctx->stats.t2_voxels += vox2;
             }
+            ctx->stats.pers_launches += launchesp;
+            ctx->stats.pers_sweeps += sweepsp;
             const Inst &last = inst[order.back()];
             ctx->stats.tile_x = last.tile.tx;
             ctx->stats.tile_y = last.tile.ty;
@@ -875,8 +959,16 @@ struct Engine {
             ctx->stats.precision = last.prec == kF64 ? PM_FP64 : PM_FP32;
             ctx->stats.tblock = groups.back().two ? 2 : 1;
         }
+        if (launchesp > 0) {
+            int hf = 0;
+            PM_HIP(hipMemcpy(&hf, ctx->d_fail, sizeof hf, hipMemcpyDeviceToHost));
+            if (hf) {
+                PM_HIP(hipMemset(ctx->d_fail, 0, sizeof(int)));
+                return fail(ctx, PM_ERR_DEVICE, "persistent sweeps: a barrier wait ran out (the state is incomplete)");
+            }
+        }
         for (const Group &g : groups)
-            for (int k = 0; k < g.count; ++k) inst[order[g.first + k]].passes += g.n1 + g.n2;
+            for (int k = 0; k < g.count; ++k) inst[order[g.first + k]].passes += g.n1 + g.n2 + g.np;
         // h_sums rows follow `order`; remap to `sel` positions
         sums_of.assign(inst.size(), nullptr);
         for (size_t r = 0; r < order.size(); ++r) sums_of[order[r]] = ctx->h_sums + r * kNumSums;
@@ -1807,6 +1899,8 @@ void pm_destroy(pm_ctx *ctx)
     (void)hipSetDevice(ctx->dev);
     for (int i = 0; i < 4; ++i)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    if (ctx->d_bar) (void)hipFree(ctx->d_bar);
+    if (ctx->d_fail) (void)hipFree(ctx->d_fail);
     for (auto &kv : ctx->allocs) (void)hipFree(kv.first);
     release_pool(ctx);
     if (ctx->h_sums) (void)hipHostFree(ctx->h_sums);

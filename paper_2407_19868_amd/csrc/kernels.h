@@ -84,6 +84,22 @@ hipError_t launch_fused_src(int tile_x, int tile_y, const InstDev *insts, int ni
 // Two fused steps per launch over output tiles of ox x oy columns (workgroups
 // of (ox + 4) x (oy + 4) threads); never reducing, never skipping.  The table
 // entries carry the decomposition of these tiles.
+// Persistent sweeps of small instances (one XCD per instance, at most
+// kPersMaxBlocks workgroups each): `nsweeps` sweeps of up to 8 instances in one
+// cooperative launch, instance j on the workgroups with blockIdx mod 8 == j.
+// bar: kPersXcds * kBarrierStride zeroed counters (the launcher clears them);
+// fail: set to 1 when a barrier wait runs out (the sweeps after it are not done).
+constexpr int kPersXcds = 8;
+constexpr int kPersMaxBlocks = 32;
+constexpr int kBarrierStride = 64;  // uint32 per counter: one per 256-byte line
+constexpr int kXccProbeBlocks = 64;
+constexpr size_t kPersL2Bytes = 3u << 20;  // largest working set swept on one XCD
+constexpr int kPersTX = 32, kPersTY = 16;    // tile of the persistent sweeps
+hipError_t launch_fused_pers(Prec prec, int tx, int ty, const InstDev *insts, int ninst, int64_t max_blocks,
+                             int parity, int nsweeps, unsigned *bar, int *fail, hipStream_t s);
+// XCD (hardware XCC id) of each of kXccProbeBlocks workgroups, into out[]
+hipError_t launch_xcc_ids(unsigned *out, hipStream_t s);
+
 hipError_t launch_fused2(Prec prec, int ox, int oy, const InstDev *insts, int ninst, int64_t nblocks, int parity,
                          hipStream_t s);
 bool fused2_tile_supported(int ox, int oy, int prec);

@@ -446,6 +446,7 @@ constexpr int kCusPerXcd = 32;
 // range reads 0 and drops a store (the hardware's range check).
 constexpr int kRsrcWord3 = 0x00020000;  // gfx9 word 3: 32-bit data format, untyped access
 constexpr int kNonTemporal = 2;         // cache policy bit: nt
+constexpr int kScopeAgent = 16;         // cache policy bit: sc1 (loads bypass the CU's L1)
 constexpr uint32_t kOffNone = 0x80000000u;  // beyond every plane (planes hold < 2^31 bytes)
 using Rsrc = __amdgpu_buffer_rsrc_t;
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
@@ -524,54 +525,19 @@ struct FusedShared {
 // are stored.  The fixed point is e* = s* - s0.  The residual of s0 + e
 // follows from linearity: F(s0 + e) = F_A(e) + d0_v / dt and
 // div(v0 + e_v) = div(e_v) - d0_p / (c2 dt); the flux sums are those of e.
-template <typename T, int TX, int TY, bool RED, bool SRC = false>
-__global__ void __launch_bounds__(TX *TY)
-k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
+// One workgroup's z-chunk of one sweep: block b of the launch (instance found
+// from the table), reading set `parity` ^ par_off.  first: the launch's first
+// sweep (the instance's `skip` applies to it only).  LAUX: cache policy of the
+// field loads (kScopeAgent in the persistent sweeps, which read what other
+// CUs wrote earlier in the same launch).
+template <typename T, int TX, int TY, bool RED, bool SRC, int LAUX = 0>
+__device__ __forceinline__ void fused_chunk(FusedShared<T, TX, TY> &sh, const InstDev *__restrict__ insts, int ninst,
+                                            int64_t b, int parity, bool first)
 {
     constexpr int NT = TX * TY;
     constexpr int PX = TX + 4, PY = TY + 4;
     constexpr int NHALO = PX * PY - NT;
     static_assert(NHALO <= NT, "one halo position per thread");
-    __shared__ FusedShared<T, TX, TY> sh;
-
-    // ---- XCD-aware order: workgroups are dispatched round-robin over the
-    // XCDs, each with its own L2.  Give each XCD a contiguous run of tiles so
-    // that the halo reads of neighbouring tiles hit the L2 that loaded them.
-    // With many tiles per plane the runs of all eight XCDs start at the same
-    // in-plane tile of different z-chunks, and the XCDs then stream the same
-    // in-plane region at once; starting XCD i's run 1/8 of its length later
-    // for each i measured up to 12 % faster there (FP32, 1024^3) and 1-2 %
-    // slower with 64 tiles per plane (256^3), hence the threshold.  Blocks are
-    // only permuted: results are unchanged.
-    //
-    // FP64 workgroups of 1024 threads run one per CU (their LDS rings take
-    // 98-114 KiB), so the chip holds 256 of them at a time.  For these the
-    // order is round-major: workgroups 8 M r ... 8 M (r + 1) - 1 (M = 32 CUs
-    // per XCD) form round r and take the contiguous tiles of that range, XCD i
-    // the i-th run of 32.  Every round then has the layout of a launch of 256
-    // tiles: 3-5 % faster than one run per XCD (three 256^3 instances, 1536^3).
-    // Blocks are only permuted: results are unchanged.
-    const int64_t nbk = gridDim.x, xcd = blockIdx.x % kNumXcd, kx = blockIdx.x / kNumXcd;
-    int64_t b;
-    if constexpr (sizeof(T) == 8 && TX * TY == 1024) {
-        constexpr int64_t M = kCusPerXcd;
-        const int64_t full = nbk / (kNumXcd * M);  // complete rounds
-        if (kx / M < full) {
-            b = (kx / M) * (kNumXcd * M) + xcd * M + (kx % M);
-        } else {
-            // the partial last round: one run per XCD over the remaining range
-            const int64_t base = full * kNumXcd * M, nr = nbk - base;
-            const int64_t qr = nr / kNumXcd, rr = nr % kNumXcd;
-            b = base + (xcd < rr ? xcd * (qr + 1) : rr * (qr + 1) + (xcd - rr) * qr) + (kx - full * M);
-        }
-    } else {
-        const int64_t q = nbk / kNumXcd, rem = nbk % kNumXcd;
-        const int64_t qx = xcd < rem ? q + 1 : q;  // length of this XCD's run
-        const bool rotate = (int64_t)insts[0].tiles_x * insts[0].tiles_y >= 256;
-        b = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) +
-            (rotate ? (kx + xcd * (qx / kNumXcd)) % qx : kx);
-    }
-
     // ---- instance of this block (ranges are sorted by blk_begin)
     int lo = 0, hi = ninst - 1;
     while (lo < hi) {
@@ -610,7 +576,7 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
     const T gu = I.axis == 0 ? (T)I.drive : T(0);
     const T gv = I.axis == 1 ? (T)I.drive : T(0);
     const T gw = I.axis == 2 ? (T)I.drive : T(0);
-    const bool skip = I.skip != 0;
+    const bool skip = first && I.skip != 0;
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -655,27 +621,27 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
         const int64_t zb = (int64_t)wrap_int(z0 - 3 + j, nz) * plane_b;
-        Uw[j] = bload<T>(rsrc_at(Uin, zb, plane_b), own_b);
-        Vw[j] = bload<T>(rsrc_at(Vin, zb, plane_b), own_b);
+        Uw[j] = bload<T, LAUX>(rsrc_at(Uin, zb, plane_b), own_b);
+        Vw[j] = bload<T, LAUX>(rsrc_at(Vin, zb, plane_b), own_b);
     }
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-        Ww[j] = bload<T>(rsrc_at(Win, (int64_t)wrap_int(z0 - 2 + j, nz) * plane_b, plane_b), own_b);
+        Ww[j] = bload<T, LAUX>(rsrc_at(Win, (int64_t)wrap_int(z0 - 2 + j, nz) * plane_b, plane_b), own_b);
     // byte offsets of planes zz .. zz + 3 (fields) and zz + 1 (codes)
     int64_t zb0 = (int64_t)wrap_int(z0 - 1, nz) * plane_b;
     int64_t zb1 = next_plane(zb0, plane_b, field_b);
     int64_t zb2 = next_plane(zb1, plane_b, field_b);
     int64_t zb3 = next_plane(zb2, plane_b, field_b);
     int64_t zc1 = (int64_t)wrap_int(z0, nz) * plane_c;
-    T pold = bload<T>(rsrc_at(Pin, zb0, plane_b), own_b);
+    T pold = bload<T, LAUX>(rsrc_at(Pin, zb0, plane_b), own_b);
     uint32_t code = 0;
     T sU = T(0), sV = T(0), sW = T(0), sP = T(0);  // correction-form terms of plane zz
     T hU = T(0), hV = T(0), hW = T(0), hP = T(0);
     if (has_halo) {
-        hU = bload<T>(rsrc_at(Uin, zb0, plane_b), hoff_b);
-        hV = bload<T>(rsrc_at(Vin, zb0, plane_b), hoff_b);
-        hW = bload<T>(rsrc_at(Win, zb1, plane_b), hoff_b);
-        if (has_ph) hP = bload<T>(rsrc_at(Pin, zb0, plane_b), hoff_b);
+        hU = bload<T, LAUX>(rsrc_at(Uin, zb0, plane_b), hoff_b);
+        hV = bload<T, LAUX>(rsrc_at(Vin, zb0, plane_b), hoff_b);
+        hW = bload<T, LAUX>(rsrc_at(Win, zb1, plane_b), hoff_b);
+        if (has_ph) hP = bload<T, LAUX>(rsrc_at(Pin, zb0, plane_b), hoff_b);
     }
     int slot = 0;                   // u, v, p slot of plane zz
     int wc = 0, wn = 1;             // w slots of planes zz and zz + 1
@@ -724,18 +690,18 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
                 bSw = bload<T, kNonTemporal>(rsrc_at(Sw, zb1, plane_b), own_b);
                 bSp = bload<T, kNonTemporal>(rsrc_at(Sp, zb1, plane_b), own_b);
             }
-            bU = bload<T>(rsrc_at(Uin, zb3, plane_b), own_b);
-            bV = bload<T>(rsrc_at(Vin, zb3, plane_b), own_b);
-            bW = bload<T>(rW2, own_b);
-            bP = bload<T>(rP1, own_b);
+            bU = bload<T, LAUX>(rsrc_at(Uin, zb3, plane_b), own_b);
+            bV = bload<T, LAUX>(rsrc_at(Vin, zb3, plane_b), own_b);
+            bW = bload<T, LAUX>(rW2, own_b);
+            bP = bload<T, LAUX>(rP1, own_b);
             bC = bload<uint16_t, kNonTemporal>(rsrc_at(codes, zc1, plane_c), own_c);
         }
         T bhU = T(0), bhV = T(0), bhW = T(0), bhP = T(0);
         if (has_halo && ahead) {
-            bhU = bload<T>(rU1, hoff_b);
-            bhV = bload<T>(rV1, hoff_b);
-            bhW = bload<T>(rW2, hoff_b);
-            if (has_ph) bhP = bload<T>(rP1, hoff_b);
+            bhU = bload<T, LAUX>(rU1, hoff_b);
+            bhV = bload<T, LAUX>(rV1, hoff_b);
+            bhW = bload<T, LAUX>(rW2, hoff_b);
+            if (has_ph) bhP = bload<T, LAUX>(rP1, hoff_b);
         }
         __syncthreads();
 
@@ -846,6 +812,57 @@ k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) expcnt(7) lgkmcnt(15)
     for (int zz = z0; zz < z1; ++zz) plane_step(zz, BoolC<true>{});
     if (RED) block_sums(acc, sh.red, I.partials + lb * kNumSums);
+}
+
+template <typename T, int TX, int TY, bool RED, bool SRC = false>
+__global__ void __launch_bounds__(TX *TY)
+k_fused(const InstDev *__restrict__ insts, int ninst, int parity)
+{
+    constexpr int NT = TX * TY;
+    constexpr int PX = TX + 4, PY = TY + 4;
+    constexpr int NHALO = PX * PY - NT;
+    static_assert(NHALO <= NT, "one halo position per thread");
+    __shared__ FusedShared<T, TX, TY> sh;
+
+    // ---- XCD-aware order: workgroups are dispatched round-robin over the
+    // XCDs, each with its own L2.  Give each XCD a contiguous run of tiles so
+    // that the halo reads of neighbouring tiles hit the L2 that loaded them.
+    // With many tiles per plane the runs of all eight XCDs start at the same
+    // in-plane tile of different z-chunks, and the XCDs then stream the same
+    // in-plane region at once; starting XCD i's run 1/8 of its length later
+    // for each i measured up to 12 % faster there (FP32, 1024^3) and 1-2 %
+    // slower with 64 tiles per plane (256^3), hence the threshold.  Blocks are
+    // only permuted: results are unchanged.
+    //
+    // FP64 workgroups of 1024 threads run one per CU (their LDS rings take
+    // 98-114 KiB), so the chip holds 256 of them at a time.  For these the
+    // order is round-major: workgroups 8 M r ... 8 M (r + 1) - 1 (M = 32 CUs
+    // per XCD) form round r and take the contiguous tiles of that range, XCD i
+    // the i-th run of 32.  Every round then has the layout of a launch of 256
+    // tiles: 3-5 % faster than one run per XCD (three 256^3 instances, 1536^3).
+    // Blocks are only permuted: results are unchanged.
+    const int64_t nbk = gridDim.x, xcd = blockIdx.x % kNumXcd, kx = blockIdx.x / kNumXcd;
+    int64_t b;
+    if constexpr (sizeof(T) == 8 && TX * TY == 1024) {
+        constexpr int64_t M = kCusPerXcd;
+        const int64_t full = nbk / (kNumXcd * M);  // complete rounds
+        if (kx / M < full) {
+            b = (kx / M) * (kNumXcd * M) + xcd * M + (kx % M);
+        } else {
+            // the partial last round: one run per XCD over the remaining range
+            const int64_t base = full * kNumXcd * M, nr = nbk - base;
+            const int64_t qr = nr / kNumXcd, rr = nr % kNumXcd;
+            b = base + (xcd < rr ? xcd * (qr + 1) : rr * (qr + 1) + (xcd - rr) * qr) + (kx - full * M);
+        }
+    } else {
+        const int64_t q = nbk / kNumXcd, rem = nbk % kNumXcd;
+        const int64_t qx = xcd < rem ? q + 1 : q;  // length of this XCD's run
+        const bool rotate = (int64_t)insts[0].tiles_x * insts[0].tiles_y >= 256;
+        b = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) +
+            (rotate ? (kx + xcd * (qx / kNumXcd)) % qx : kx);
+    }
+
+    fused_chunk<T, TX, TY, RED, SRC>(sh, insts, ninst, b, parity, true);
 }
 
 // ============================================================== two sweeps per pass
@@ -1333,6 +1350,128 @@ hipError_t launch_fused_src(int tx, int ty, const InstDev *insts, int ninst, int
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
     if (!fused_tile_supported(tx, ty, kF32)) return hipErrorInvalidValue;
     return launch_fused_t<float, true>(tx, ty, insts, ninst, nblocks, parity, reduce, s, alone);
+}
+
+// ============================================================== persistent sweeps
+
+__global__ void k_zero_u32(unsigned *__restrict__ p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+// Polls of a barrier wait before it gives up (each poll is an L2 atomic round
+// trip, so this is tens of milliseconds against a wait of about a microsecond).
+constexpr unsigned kBarrierSpins = 1u << 16;
+
+//
+// Small instances are latency-bound: a sweep of a 32^3 grid is a few plane
+// steps per workgroup, and a launch costs more than that.  Such an instance
+// runs a block of sweeps inside one cooperative launch on one XCD: instance j
+// of the launch (j < 8) takes the workgroups with blockIdx mod 8 == j (the
+// dispatcher places workgroup i on XCD i mod 8; the engine checks this once
+// per device), and its workgroups meet at a barrier between sweeps.  On one
+// XCD every store lands in that XCD's L2, shared by its CUs, so the barrier
+// needs no L2 write-back: each workgroup completes its stores, counts itself
+// in with an atomic in L2 and polls the count with atomics in L2.  Its field
+// loads carry the sc1 policy bit, which reads them from L2 past the CU's L1:
+// plain loads after such a barrier returned stale L1 data on nearly every
+// read, and an acquire fence (L1 and L2 invalidation) instead cost 12 us per
+// barrier.  A barrier costs 0.7-1.1 us with 8-32 workgroups, against 3.7 us
+// with 32 for one over the whole chip (whose L2s are not coherent with each
+// other).
+
+// Barrier among the `target / round` workgroups of one XCD; the count only
+// grows (target = workgroups x barriers so far).  Polling adds `zero` (a
+// launch argument, 0) so that it stays an atomic.  A wait that runs out sets
+// *fail and returns false: the caller leaves the kernel.
+__device__ __forceinline__ bool xcd_barrier(unsigned *cnt, unsigned target, unsigned zero, int *fail)
+{
+    __shared__ int s_ok;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores and loads are complete
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        unsigned spins = 0;
+        int ok = 1;
+        while (__hip_atomic_fetch_add(cnt, zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+            if (++spins > kBarrierSpins) {
+                __hip_atomic_store(fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+        }
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// `nsweeps` sweeps of up to 8 instances, instance j on XCD j; sweep k reads set
+// (parity + k) & 1.  Only the first sweep applies an instance's `skip`.
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY)
+k_fused_pers(const InstDev *__restrict__ insts, int ninst, int parity, int nsweeps, unsigned *bar, unsigned zero,
+             int *fail)
+{
+    const int j = (int)(blockIdx.x % kNumXcd);
+    if (j >= ninst) return;
+    const InstDev &I = insts[j];
+    const int64_t lb = blockIdx.x / kNumXcd;
+    if (lb >= I.nblocks) return;
+    __shared__ FusedShared<T, TX, TY> sh;
+    unsigned *const cnt = bar + kBarrierStride * j;
+    const unsigned nb = (unsigned)I.nblocks;
+    for (int k = 0; k < nsweeps; ++k) {
+        fused_chunk<T, TX, TY, false, false, kScopeAgent>(sh, insts, ninst, I.blk_begin + lb, parity ^ (k & 1),
+                                                          k == 0);
+        if (k + 1 < nsweeps && !xcd_barrier(cnt, nb * (unsigned)(k + 1), zero, fail)) return;
+    }
+}
+
+template <typename T>
+static hipError_t launch_fused_pers_t(int tx, int ty, const InstDev *insts, int ninst, int64_t max_blocks, int parity,
+                                      int nsweeps, unsigned *bar, int *fail, hipStream_t s)
+{
+    const dim3 grid((unsigned)(kNumXcd * max_blocks));
+    unsigned zero = 0u;
+    void *args[] = {(void *)&insts, (void *)&ninst, (void *)&parity, (void *)&nsweeps, (void *)&bar, (void *)&zero,
+                    (void *)&fail};
+#define PS_PERS_CASE(TX_, TY_)                                                                                    \
+    if (tx == TX_ && ty == TY_)                                                                                  \
+        return hipLaunchCooperativeKernel((const void *)k_fused_pers<T, TX_, TY_>, grid, dim3(TX_ * TY_), args, 0, s);
+    PS_PERS_CASE(128, 8)
+    PS_PERS_CASE(64, 8)
+    PS_PERS_CASE(64, 16)
+    PS_PERS_CASE(32, 8)
+    PS_PERS_CASE(32, 16)
+#undef PS_PERS_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fused_pers(Prec prec, int tx, int ty, const InstDev *insts, int ninst, int64_t max_blocks,
+                             int parity, int nsweeps, unsigned *bar, int *fail, hipStream_t s)
+{
+    if (ninst < 1 || ninst > kNumXcd || max_blocks < 1 || max_blocks > kPersMaxBlocks || nsweeps < 1)
+        return hipErrorInvalidValue;
+    if (!fused_tile_supported(tx, ty, prec)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, bar, (int)(kNumXcd * kBarrierStride));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return prec == kF64 ? launch_fused_pers_t<double>(tx, ty, insts, ninst, max_blocks, parity, nsweeps, bar, fail, s)
+                        : launch_fused_pers_t<float>(tx, ty, insts, ninst, max_blocks, parity, nsweeps, bar, fail, s);
+}
+
+// The XCD of every workgroup of a 64-workgroup launch (hardware register
+// XCC_ID), for the placement check of the persistent sweeps.
+__global__ void k_xcc_ids(unsigned *out)
+{
+    if (threadIdx.x == 0) out[blockIdx.x] = __builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 0xfu;
+}
+
+hipError_t launch_xcc_ids(unsigned *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_xcc_ids, dim3(kXccProbeBlocks), dim3(64), 0, s, out);
+    return hipGetLastError();
 }
 
 // ============================================================== reductions
