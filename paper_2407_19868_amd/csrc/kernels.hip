@@ -1353,6 +1353,22 @@ hipError_t launch_fused_src(int tx, int ty, const InstDev *insts, int ninst, int
 }
 
 // ============================================================== persistent sweeps
+//
+// A small instance can run a block of sweeps inside one cooperative launch on
+// one XCD: instance j of the launch (j < 8) takes the workgroups with blockIdx
+// mod 8 == j (the dispatcher places workgroup i on XCD i mod 8; the engine
+// checks this once per context), and its workgroups meet at a barrier between
+// sweeps.  On one XCD every store lands in that XCD's L2, shared by its CUs, so
+// the barrier needs no L2 write-back: each workgroup completes its stores,
+// counts itself in with an atomic in L2 and polls the count with atomics in L2.
+// Its field loads carry the sc1 policy bit, which reads them from L2 past the
+// CU's L1: plain loads after such a barrier returned stale L1 data on nearly
+// every read, and an acquire fence (L1 and L2 invalidation) instead cost 12 us
+// per barrier.  A barrier costs 0.7-1.1 us with 8-32 workgroups, against 3.7 us
+// with 32 for one over the whole chip (whose L2s are not coherent with each
+// other).  The launch saves the launch gaps of a block but keeps an instance on
+// an eighth of the chip: it gains where several small instances run side by
+// side and loses on a single one, so the engine uses it only when asked.
 
 __global__ void k_zero_u32(unsigned *__restrict__ p, int n)
 {
@@ -1362,23 +1378,6 @@ __global__ void k_zero_u32(unsigned *__restrict__ p, int n)
 // Polls of a barrier wait before it gives up (each poll is an L2 atomic round
 // trip, so this is tens of milliseconds against a wait of about a microsecond).
 constexpr unsigned kBarrierSpins = 1u << 16;
-
-//
-// Small instances are latency-bound: a sweep of a 32^3 grid is a few plane
-// steps per workgroup, and a launch costs more than that.  Such an instance
-// runs a block of sweeps inside one cooperative launch on one XCD: instance j
-// of the launch (j < 8) takes the workgroups with blockIdx mod 8 == j (the
-// dispatcher places workgroup i on XCD i mod 8; the engine checks this once
-// per device), and its workgroups meet at a barrier between sweeps.  On one
-// XCD every store lands in that XCD's L2, shared by its CUs, so the barrier
-// needs no L2 write-back: each workgroup completes its stores, counts itself
-// in with an atomic in L2 and polls the count with atomics in L2.  Its field
-// loads carry the sc1 policy bit, which reads them from L2 past the CU's L1:
-// plain loads after such a barrier returned stale L1 data on nearly every
-// read, and an acquire fence (L1 and L2 invalidation) instead cost 12 us per
-// barrier.  A barrier costs 0.7-1.1 us with 8-32 workgroups, against 3.7 us
-// with 32 for one over the whole chip (whose L2s are not coherent with each
-// other).
 
 // Barrier among the `target / round` workgroups of one XCD; the count only
 // grows (target = workgroups x barriers so far).  Polling adds `zero` (a
@@ -1439,10 +1438,6 @@ static hipError_t launch_fused_pers_t(int tx, int ty, const InstDev *insts, int 
 #define PS_PERS_CASE(TX_, TY_)                                                                                    \
     if (tx == TX_ && ty == TY_)                                                                                  \
         return hipLaunchCooperativeKernel((const void *)k_fused_pers<T, TX_, TY_>, grid, dim3(TX_ * TY_), args, 0, s);
-    PS_PERS_CASE(128, 8)
-    PS_PERS_CASE(64, 8)
-    PS_PERS_CASE(64, 16)
-    PS_PERS_CASE(32, 8)
     PS_PERS_CASE(32, 16)
 #undef PS_PERS_CASE
     return hipErrorInvalidValue;
@@ -1453,7 +1448,7 @@ hipError_t launch_fused_pers(Prec prec, int tx, int ty, const InstDev *insts, in
 {
     if (ninst < 1 || ninst > kNumXcd || max_blocks < 1 || max_blocks > kPersMaxBlocks || nsweeps < 1)
         return hipErrorInvalidValue;
-    if (!fused_tile_supported(tx, ty, prec)) return hipErrorInvalidValue;
+    if (tx != kPersTX || ty != kPersTY) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, bar, (int)(kNumXcd * kBarrierStride));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
