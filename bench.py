@@ -272,6 +272,33 @@ def series_workload(args) -> dict:
             log(f"[bench] decay: r {rr[-1]:.3e} after {r.sweeps} sweeps, {1000 * rate:.3f} e-folds/1000 sweeps")
             del f
             torch.cuda.empty_cache()
+        converge = None
+        if args.converge_sweeps > 0:
+            # one load axis solved to the relative change of |q| between checks
+            # below 1e-6, the criterion of the paper's large-domain runs (§7.1):
+            # FP32 sweeps until it holds, then FP64 sweeps confirm it
+            ctx.trim()
+            log(f"[bench] 1536^3 solve along x to eps_q < 1e-6, FP32-DC, budget {args.converge_sweeps} sweeps")
+            t0 = time.perf_counter()
+            r = ctx.solve(mask, 0, ps.params(precision=ps.FP32_DC, stop_rule=1, tol=1e-6,
+                                             max_sweeps=args.converge_sweeps, progress=10))
+            wall = time.perf_counter() - t0
+            st = ctx.last_stats()
+            eps = np.asarray(r.hist_eps, dtype=np.float64)
+            first = int(r.hist_sweep[np.argmax(eps < 1e-6)]) if bool((eps < 1e-6).any()) else None
+            converge = {"status": r.status, "stop_rule": "eps_q < 1e-6", "sweeps": int(r.sweeps),
+                        "seconds": round(wall, 1), "first_check_below_tol": first,
+                        "eps_q_last": float(eps[-1]) if len(eps) else None,
+                        "r_last": float(r.hist_r[-1]) if len(r.hist_r) else None,
+                        "dc_promoted_for_memory": int(st["dc_promoted_for_memory"]),
+                        "library_peak_bytes": int(st["peak_bytes"]),
+                        "k_col": [float(f"{x:.10g}") for x in r.kcol],
+                        "eps_q_every_1000": [[int(a), float(f"{b:.4g}")] for a, b in zip(r.hist_sweep, eps)
+                                             if int(a) % 1000 == 0]}
+            log(f"[bench] 1536^3 solve: {wall:.1f} s, status {r.status}, {r.sweeps} sweeps, "
+                f"eps_q {converge['eps_q_last']:.3e}, r {converge['r_last']:.3e}")
+            del r
+            torch.cuda.empty_cache()
         tensor = None
         if args.tensor_sweeps > 0:
             # the full tensor call at this size: the three load cases do not fit beside
@@ -297,7 +324,7 @@ def series_workload(args) -> dict:
                 "config": {"workload": "overlapping spheres 1536^3, radius U[5,12], porosity 0.20, seed 5; "
                                        "load axis x; fields from rest",
                            "grid": [1536, 1536, 1536], "porosity": round(float(1 - mask_np.mean()), 4)},
-                "forms": res, "residual_decay": decay, "tensor": tensor}
+                "forms": res, "residual_decay": decay, "converged_axis": converge, "tensor": tensor}
 
     if args.workload == "precipitation":
         log("[bench] generating the precipitation series (16 states, 1024x512x16 + walls)")
@@ -401,6 +428,8 @@ def main() -> int:
                     help="spheres1536: also call pm_tensor (FP32-DC) with this sweep budget per load axis")
     ap.add_argument("--decay-sweeps", type=int, default=0,
                     help="spheres1536: FP32 solve of this many sweeps to extrapolate the sweeps to r < 1e-8")
+    ap.add_argument("--converge-sweeps", type=int, default=0,
+                    help="spheres1536: FP32-DC solve along x to eps_q < 1e-6 within this sweep budget")
     ap.add_argument("--pore-cleanup", type=int, choices=[0, 1], default=0,
                     help="series workloads: sweep only the pore components that percolate along the load axis")
     ap.add_argument("--calibrate-copy", action="store_true",

@@ -424,6 +424,34 @@ __device__ __forceinline__ void fill_code_lut(uint32_t *lut, int tid)
     }
 }
 
+// The larger table, for workgroups of 1024 threads (two fills per thread):
+// the (u, v) part of the code word for each r = iu + 37 iv (1369 entries),
+// then the w part for each iw (37).  One division by a constant and two
+// reads decode a code, against two divisions (one of them a quarter-rate
+// multiply-high sequence) and three reads with the 111-entry table, which
+// stays with the smaller workgroups: filling 1406 entries with 256 threads
+// made the latency-bound 32^3 solve slower.
+constexpr int kCodeLutBig = (int)kPackUV + (int)kPackBase;
+
+template <int NT>
+__device__ __forceinline__ void fill_code_lut_big(uint32_t *lut, int tid)
+{
+    for (int i = tid; i < kCodeLutBig; i += NT) {
+        if (i < (int)kPackUV) {
+            const uint32_t iv = (uint32_t)i / kPackBase, iu = (uint32_t)i - iv * kPackBase;
+            lut[i] = unpack_component(iu) | unpack_component(iv) << kCodeBits;
+        } else {
+            lut[i] = unpack_component((uint32_t)i - kPackUV) << (2 * kCodeBits);
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t lut_code_big(const uint32_t *lut, uint32_t p)
+{
+    const uint32_t iw = p / kPackUV, r = p - iw * kPackUV;
+    return lut[r] | lut[kPackUV + iw];
+}
+
 __device__ __forceinline__ uint32_t lut_code(const uint32_t *lut, uint32_t p)
 {
     const uint32_t iw = p / kPackUV, r = p - iw * kPackUV, iv = r / kPackBase, iu = r - iv * kPackBase;
@@ -510,7 +538,8 @@ struct FusedShared {
     T p[2][PP];
     T w[3][PP];
     Coef4<T> tab[8];
-    uint32_t lut[kCodeLut];
+    static constexpr bool kBig = TX * TY >= 1024;
+    uint32_t lut[kBig ? kCodeLutBig : kCodeLut];
     double red[kNumSums * (TX * TY / 64)];
 };
 
@@ -581,7 +610,10 @@ __device__ __forceinline__ void fused_chunk(FusedShared<T, TX, TY> &sh, const In
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     fill_coef4(sh.tab, tid);
-    fill_code_lut(sh.lut, tid);
+    if constexpr (FusedShared<T, TX, TY>::kBig)
+        fill_code_lut_big<NT>(sh.lut, tid);
+    else
+        fill_code_lut(sh.lut, tid);
 
     // ---- own column (inactive threads hold the wrapped column: LDS stays periodic)
     const int gx = x0 + tx, gy = y0 + ty;
@@ -655,8 +687,13 @@ __device__ __forceinline__ void fused_chunk(FusedShared<T, TX, TY> &sh, const In
     // counter (s_waitcnt vmcnt) counts loads and stores in issue order, and a
     // path without the stores made the compiler wait for each step's stores
     // to complete before the loads of the next plane could be used (10 %).
-    auto plane_step = [&](const int zz, auto body_c) __attribute__((always_inline)) {
+    // `ahead` is false only for the chunk's last plane, which loads nothing
+    // for a next one; peeling it too leaves the loop without a branch around
+    // its loads and without zeroing their registers (13 of 149 vector ALU
+    // instructions per FP32 step, with the larger code table).
+    auto plane_step = [&](const int zz, auto body_c, auto ahead_c) __attribute__((always_inline)) {
         constexpr bool body = decltype(body_c)::value;
+        constexpr bool ahead = decltype(ahead_c)::value;
         T *const su = sh.u[slot];
         T *const sv = sh.v[slot];
         T *const sp = sh.p[slot];
@@ -676,8 +713,7 @@ __device__ __forceinline__ void fused_chunk(FusedShared<T, TX, TY> &sh, const In
         }
 
         // ---- loads for iteration zz + 1 (planes wrap, so every address is
-        // valid); the last iteration of the chunk needs none
-        const bool ahead = zz + 1 < z1;
+        // valid)
         T bU = T(0), bV = T(0), bW = T(0), bP = T(0);
         T bSu = T(0), bSv = T(0), bSw = T(0), bSp = T(0);
         uint32_t bC = 0;
@@ -720,7 +756,11 @@ __device__ __forceinline__ void fused_chunk(FusedShared<T, TX, TY> &sh, const In
             const T pym = (skip || held.ym || hz) ? sp[cl - PX] : fma(-c2dt, dym, sp[cl - PX]);
             bstore<T, kNonTemporal>(SRC ? pn + sP : pn, rsrc_at(Pout, zb0, plane_b), own_b);
             // u: own axis x, across y (LDS) and z (registers)
-            const uint32_t word = lut_code(sh.lut, code);
+            uint32_t word;
+            if constexpr (FusedShared<T, TX, TY>::kBig)
+                word = lut_code_big(sh.lut, code);
+            else
+                word = lut_code(sh.lut, code);
             const uint32_t cu = word;
             const T u0 = Uw[2];
             const T u_d2x = d2_own(su[cl - 1], u0, su[cl + 1]);
@@ -806,11 +846,12 @@ __device__ __forceinline__ void fused_chunk(FusedShared<T, TX, TY> &sh, const In
         wc = wn;
         wn = (wn == 2) ? 0 : wn + 1;
     };
-    plane_step(z0 - 1, BoolC<false>{});
+    plane_step(z0 - 1, BoolC<false>{}, BoolC<true>{});  // z1 > z0: loads for z0
     // the prologue's loads land in the registers the loop carries: complete
     // them here, or the loop head would wait as if they were still in flight
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) expcnt(7) lgkmcnt(15)
-    for (int zz = z0; zz < z1; ++zz) plane_step(zz, BoolC<true>{});
+    for (int zz = z0; zz < z1 - 1; ++zz) plane_step(zz, BoolC<true>{}, BoolC<true>{});
+    plane_step(z1 - 1, BoolC<true>{}, BoolC<false>{});
     if (RED) block_sums(acc, sh.red, I.partials + lb * kNumSums);
 }
 
