@@ -65,7 +65,10 @@ typedef enum {
     PM_FP32 = 1,    /* FP32 fields and arithmetic, FP64 reductions                     */
     PM_FP32_DC = 2  /* FP32 phase until the residual stalls at its rounding floor,
                        then an FP64 defect correction until tol (pm_params.dc_form:
-                       FP32 sweeps of the correction, or FP64 sweeps)               */
+                       FP32 sweeps of the correction, or FP64 sweeps).  An FP32
+                       phase that meets the stop rule first (with stop_rule 1:
+                       eps_q < tol at a check where r reached a new minimum)
+                       hands over to FP64 sweeps, which must meet it again      */
 } pm_precision;
 
 typedef enum {

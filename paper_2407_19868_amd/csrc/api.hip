@@ -1219,6 +1219,12 @@ struct Engine {
         // Near its floor an FP32 iterate stagnates: q stops changing and eps_q
         // reads 0 without convergence, so there eps_q does not count.
         const bool met = prm->stop_rule == 0 ? r < prm->tol : eps < prm->tol && !(fp32_phase && near_floor);
+        // A hand-over to FP64, which then meets the stop rule by itself, may
+        // also follow eps_q near the floor while r still reaches a new minimum
+        // at every check, which a stagnating iterate does not (the 1536^3
+        // packing: eps_q < 1e-6 at 40,500 FP32 sweeps with r = 1.5e-5, within
+        // three decades of its floor and still falling 5 % per 1000 sweeps)
+        const bool met_dc = met || (prm->stop_rule == 1 && eps < prm->tol && in.stall == 0);
         const bool floor = fp32_phase && ((near_floor && (in.stall >= 5 || at_fp32_floor(in))) || in.stall >= 20);
         if (in.dc && fp32_phase && in.delta) {
             // correction form: s0 + e meets the stop rule, or e sits at its
@@ -1231,7 +1237,7 @@ struct Engine {
         } else if (in.dc && fp32_phase) {
             // hand over once the FP32 iterate meets the stop rule (FP64 confirms
             // it) or sits at its rounding floor
-            if (met) return promote(in);
+            if (met_dc) return promote(in);
             if (floor) {
                 if (prm->dc_form == 1) return promote(in);
                 in.to_delta = true;  // after this round of checks: it launches a sweep

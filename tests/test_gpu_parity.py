@@ -456,6 +456,28 @@ def test_fp32_dc_correction_form_eps_rule(ctx):
     assert normwise(g.kcol, f.kcol) <= 1e-8
 
 
+def test_fp32_dc_eps_rule_hands_over_while_r_falls(ctx):
+    """eps_q < tol reached by the FP32 phase within three decades of its rounding
+    floor, while r still makes a new minimum at every check, hands over to FP64,
+    which confirms the rule: the solve ends where the FP64 solve does (96^3
+    packing, eps_q < 1e-6: FP64 4300 sweeps; a hand-over that waited for the
+    FP32 floor ran 7400 sweeps)."""
+    mask = synth.spheres(96, 96, 96, 4.0, 8.0, 0.25, 9)
+    m = ps.to_device(mask)
+    prm = dict(stop_rule=1, tol=1e-6)
+    f = ctx.solve(m, 0, ps.params(**prm))
+    g = ctx.solve(m, 0, ps.params(precision=ps.FP32_DC, **prm))
+    assert f.status == g.status == "OK"
+    hs = np.asarray(g.hist_sweep)
+    hand = hs[1:][np.diff(hs) == 0]
+    assert len(hand) == 1 and hand[0] <= f.sweeps + 100  # one hand-over, FP32 stopped on eps_q
+    assert g.sweeps <= f.sweeps + 300
+    assert g.hist_eps[-1] < 1e-6
+    # both stop on the same rule a few checks apart: k agrees to the size of the
+    # flux change that the rule still allows over those checks
+    assert normwise(g.kcol, f.kcol) <= 1e-5
+
+
 def test_fp32_eps_rule_does_not_stop_on_stagnation(ctx):
     """At its rounding floor an FP32 iterate stops changing and eps_q reads 0:
     that is not convergence (the FP32 form ends NOT_CONVERGED at the floor)."""
