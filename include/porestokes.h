@@ -158,11 +158,11 @@ typedef struct {
                            persistent launch, instance j of up to 8 on XCD j, 32x16
                            tiles, at most 32 workgroups per instance, a barrier in
                            the XCD's L2 between sweeps (solves, tensors and batches;
-                           results are bitwise the same).  On MI355X it gains where
-                           several small instances run side by side (three 32^3
-                           load cases: 11.0 against 14.1 ms) and loses on a single
-                           FP64 32^3 solve (7.0 against 6.2 us per sweep).  0: one
-                           launch per sweep.                     default 0            */
+                           results are bitwise the same).  On MI355X, against one
+                           launch per sweep with 32x8 tiles and one-plane chunks,
+                           it is no faster: 32^3 FP64 solve 7.0 against 5.4 us
+                           per sweep, three 32^3 load cases 10.9 against
+                           10.1-11.2 ms.  0: one launch per sweep.  default 0    */
 } pm_params;
 
 /* Residual history: one record per check.  Host arrays of length cap owned by
