@@ -352,8 +352,9 @@ def series_workload(args) -> dict:
                   "flowing_fraction": [round(p["n_flowing"][j] / max(p["n_pore"], 1), 4) for j in range(3)]}
                  for i, p in enumerate(pores)]
     log(f"[bench] pore connectivity of {len(masks)} states: {pores_s:.2f} s")
+    rule = {"stop_rule": 1, "tol": args.tol or 1e-6} if args.stop_rule == "eps" else {"stop_rule": 0, "tol": args.tol or 1e-8}
     prm = ps.params(precision=ps.FP32_DC, max_sweeps=args.max_sweeps, autotune=1, progress=20,
-                    pore_cleanup=args.pore_cleanup)
+                    pore_cleanup=args.pore_cleanup, **rule)
     if args.workload == "foam":
         # tune outside the timed solve (one pass per distinct shape)
         for i, m in enumerate(masks):
@@ -369,6 +370,7 @@ def series_workload(args) -> dict:
     vox = sum(int(states[i // len(axes)].size) * r["sweeps"] for i, r in enumerate(res))
     inst = [{"state": i // len(axes), "axis": axes[i % len(axes)], "status": r["status"],
              "sweeps": r["sweeps"], "r_last": float(r["r"][-1]) if len(r["r"]) else None,
+             "eps_q_last": float(r["eps"][-1]) if len(r["eps"]) else None,
              "k_col": [float(f"{x:.8g}") for x in r["kcol"]]} for i, r in enumerate(res)]
     log(f"[bench] {args.workload}: {wall:.2f} s for {len(res)} instances, status {status}")
     seq = None
@@ -397,7 +399,8 @@ def series_workload(args) -> dict:
             "gvox_per_s_whole_job": round(vox / wall / 1e9, 2),
             "sweep_kernel_ms": round(st["sweep_ms"], 1),
             "config": {"workload": desc, "instances": len(res), "max_sweeps": args.max_sweeps,
-                       "pore_cleanup": args.pore_cleanup},
+                       "pore_cleanup": args.pore_cleanup,
+                       "stop_rule": ("eps_q < %g" if rule["stop_rule"] else "r < %g") % rule["tol"]},
             "pore_connectivity_s": round(pores_s, 3), "pores": pore_info, "batched_vs_sequential": seq,
             "instances": inst}
 
@@ -430,6 +433,10 @@ def main() -> int:
                     help="spheres1536: FP32 solve of this many sweeps to extrapolate the sweeps to r < 1e-8")
     ap.add_argument("--converge-sweeps", type=int, default=0,
                     help="spheres1536: FP32-DC solve along x to eps_q < 1e-6 within this sweep budget")
+    ap.add_argument("--stop-rule", choices=["r", "eps"], default="r",
+                    help="series workloads: r < tol (default 1e-8), or the relative change of |q| between "
+                         "checks below tol (default 1e-6, the criterion of the paper's application runs)")
+    ap.add_argument("--tol", type=float, default=0.0, help="series workloads: tolerance of --stop-rule (0: its default)")
     ap.add_argument("--pore-cleanup", type=int, choices=[0, 1], default=0,
                     help="series workloads: sweep only the pore components that percolate along the load axis")
     ap.add_argument("--calibrate-copy", action="store_true",

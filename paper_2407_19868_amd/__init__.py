@@ -502,7 +502,8 @@ class Context:
             hn = hs[i].n
             sw_, r_, e_, q_ = keep[i][1]
             out.append({"status": STATUS_NAMES[arr[i].status], "kcol": np.array(arr[i].k_col[:]),
-                        "sweeps": int(arr[i].sweeps), "sweep": sw_[:hn].copy(), "r": r_[:hn].copy()})
+                        "sweeps": int(arr[i].sweeps), "sweep": sw_[:hn].copy(), "r": r_[:hn].copy(),
+                        "eps": e_[:hn].copy()})
         return STATUS_NAMES[st], out
 
 
