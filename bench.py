@@ -278,15 +278,16 @@ def series_workload(args) -> dict:
             # below 1e-6, the criterion of the paper's large-domain runs (§7.1):
             # FP32 sweeps until it holds, then FP64 sweeps confirm it
             ctx.trim()
-            log(f"[bench] 1536^3 solve along x to eps_q < 1e-6, FP32-DC, budget {args.converge_sweeps} sweeps")
+            ax = args.converge_axis
+            log(f"[bench] 1536^3 solve along {'xyz'[ax]} to eps_q < 1e-6, FP32-DC, budget {args.converge_sweeps} sweeps")
             t0 = time.perf_counter()
-            r = ctx.solve(mask, 0, ps.params(precision=ps.FP32_DC, stop_rule=1, tol=1e-6,
-                                             max_sweeps=args.converge_sweeps, progress=10))
+            r = ctx.solve(mask, ax, ps.params(precision=ps.FP32_DC, stop_rule=1, tol=1e-6,
+                                              max_sweeps=args.converge_sweeps, progress=10))
             wall = time.perf_counter() - t0
             st = ctx.last_stats()
             eps = np.asarray(r.hist_eps, dtype=np.float64)
             first = int(r.hist_sweep[np.argmax(eps < 1e-6)]) if bool((eps < 1e-6).any()) else None
-            converge = {"status": r.status, "stop_rule": "eps_q < 1e-6", "sweeps": int(r.sweeps),
+            converge = {"axis": "xyz"[ax], "status": r.status, "stop_rule": "eps_q < 1e-6", "sweeps": int(r.sweeps),
                         "seconds": round(wall, 1), "first_check_below_tol": first,
                         "eps_q_last": float(eps[-1]) if len(eps) else None,
                         "r_last": float(r.hist_r[-1]) if len(r.hist_r) else None,
@@ -432,7 +433,9 @@ def main() -> int:
     ap.add_argument("--decay-sweeps", type=int, default=0,
                     help="spheres1536: FP32 solve of this many sweeps to extrapolate the sweeps to r < 1e-8")
     ap.add_argument("--converge-sweeps", type=int, default=0,
-                    help="spheres1536: FP32-DC solve along x to eps_q < 1e-6 within this sweep budget")
+                    help="spheres1536: FP32-DC solve along --converge-axis to eps_q < 1e-6 within this sweep budget")
+    ap.add_argument("--converge-axis", type=int, choices=[0, 1, 2], default=0,
+                    help="spheres1536: load axis of the --converge-sweeps solve (0 = x)")
     ap.add_argument("--stop-rule", choices=["r", "eps"], default="r",
                     help="series workloads: r < tol (default 1e-8), or the relative change of |q| between "
                          "checks below tol (default 1e-6, the criterion of the paper's application runs)")
