@@ -341,6 +341,10 @@ def series_workload(args) -> dict:
         desc = ("open-cell foam: 512^3 Voronoi-edge struts (200 seeds, radius 3, seed 4), 8 strain "
                 "states rescaled along z to 512..384 planes; 3 load axes; 24 instances batched, "
                 "autotuned decomposition")
+    if args.states > 0:
+        # the first states only (their instances keep the series' numbering)
+        states = states[:args.states]
+        desc += f"; first {len(states)} state(s) only"
     masks = [ps.to_device(m) for m in states]
     probs = [(m, a) for m in masks for a in axes]
     # pore connectivity of every state (the analysis that pore_cleanup runs inside the solve)
@@ -440,6 +444,7 @@ def main() -> int:
                     help="series workloads: r < tol (default 1e-8), or the relative change of |q| between "
                          "checks below tol (default 1e-6, the criterion of the paper's application runs)")
     ap.add_argument("--tol", type=float, default=0.0, help="series workloads: tolerance of --stop-rule (0: its default)")
+    ap.add_argument("--states", type=int, default=0, help="series workloads: solve only the first N states (0: all)")
     ap.add_argument("--pore-cleanup", type=int, choices=[0, 1], default=0,
                     help="series workloads: sweep only the pore components that percolate along the load axis")
     ap.add_argument("--calibrate-copy", action="store_true",
