@@ -68,7 +68,9 @@ typedef enum {
                        FP32 sweeps of the correction, or FP64 sweeps).  An FP32
                        phase that meets the stop rule first (with stop_rule 1:
                        eps_q < tol at a check where r reached a new minimum)
-                       hands over to FP64 sweeps, which must meet it again      */
+                       hands over to FP64 sweeps, which must meet it again;
+                       eps_q < tol at other checks ends the FP32 phase as the
+                       floor does                                               */
 } pm_precision;
 
 typedef enum {
