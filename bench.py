@@ -279,7 +279,8 @@ def series_workload(args) -> dict:
             # FP32 sweeps until it holds, then FP64 sweeps confirm it
             ctx.trim()
             ax = args.converge_axis
-            log(f"[bench] 1536^3 solve along {'xyz'[ax]} to eps_q < 1e-6, FP32-DC, budget {args.converge_sweeps} sweeps")
+            log(f"[bench] 1536^3 solve along {'xyz'[ax]} to eps_q < 1e-6, FP32-DC, "
+                f"budget {args.converge_sweeps} sweeps")
             t0 = time.perf_counter()
             r = ctx.solve(mask, ax, ps.params(precision=ps.FP32_DC, stop_rule=1, tol=1e-6,
                                               max_sweeps=args.converge_sweeps, progress=10))
@@ -357,7 +358,10 @@ def series_workload(args) -> dict:
                   "flowing_fraction": [round(p["n_flowing"][j] / max(p["n_pore"], 1), 4) for j in range(3)]}
                  for i, p in enumerate(pores)]
     log(f"[bench] pore connectivity of {len(masks)} states: {pores_s:.2f} s")
-    rule = {"stop_rule": 1, "tol": args.tol or 1e-6} if args.stop_rule == "eps" else {"stop_rule": 0, "tol": args.tol or 1e-8}
+    if args.stop_rule == "eps":
+        rule = {"stop_rule": 1, "tol": args.tol or 1e-6}
+    else:
+        rule = {"stop_rule": 0, "tol": args.tol or 1e-8}
     prm = ps.params(precision=ps.FP32_DC, max_sweeps=args.max_sweeps, autotune=1, progress=20,
                     pore_cleanup=args.pore_cleanup, **rule)
     if args.workload == "foam":
@@ -443,7 +447,8 @@ def main() -> int:
     ap.add_argument("--stop-rule", choices=["r", "eps"], default="r",
                     help="series workloads: r < tol (default 1e-8), or the relative change of |q| between "
                          "checks below tol (default 1e-6, the criterion of the paper's application runs)")
-    ap.add_argument("--tol", type=float, default=0.0, help="series workloads: tolerance of --stop-rule (0: its default)")
+    ap.add_argument("--tol", type=float, default=0.0,
+                    help="series workloads: tolerance of --stop-rule (0: its default)")
     ap.add_argument("--states", type=int, default=0, help="series workloads: solve only the first N states (0: all)")
     ap.add_argument("--pore-cleanup", type=int, choices=[0, 1], default=0,
                     help="series workloads: sweep only the pore components that percolate along the load axis")
