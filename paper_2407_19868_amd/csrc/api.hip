@@ -19,6 +19,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "porestokes.h"
+#include "stopping.h"
 
 using namespace ps;
 
@@ -1216,51 +1217,36 @@ struct Engine {
         // (in the correction form: 2^-24 |e| / (dt G))
         const double r_floor = std::ldexp(in.delta ? qe : qn, -24) / (prm->dt * prm->drive);
         const bool near_floor = r < 1e3 * r_floor;
-        // Near its floor an FP32 iterate stagnates: q stops changing and eps_q
-        // reads 0 without convergence, so there eps_q does not count.
-        const bool met = prm->stop_rule == 0 ? r < prm->tol : eps < prm->tol && !(fp32_phase && near_floor);
-        // A hand-over to FP64, which then meets the stop rule by itself, may
-        // also follow eps_q near the floor while r still reaches a new minimum
-        // at every check, which a stagnating iterate does not (the 1536^3
-        // packing: eps_q < 1e-6 at 40,500 FP32 sweeps with r = 1.5e-5, within
-        // three decades of its floor and still falling 5 % per 1000 sweeps)
-        const bool met_dc = met || (prm->stop_rule == 1 && eps < prm->tol && in.stall == 0);
-        const bool floor = fp32_phase && ((near_floor && (in.stall >= 5 || at_fp32_floor(in))) || in.stall >= 20);
-        if (in.dc && fp32_phase && in.delta) {
-            // correction form: s0 + e meets the stop rule, or e sits at its
-            // own rounding floor (s0 + e continues in FP64).  eps_q < tol that
-            // the floor gate does not count also goes on in FP64, which must
-            // meet the rule once more (the 512^3 foam along x ended its budget
-            // in this form with eps_q = 1.6e-8 and r still falling)
-            if (met) {
-                in.status = PM_OK;
-                return finalize(in);
-            }
-            if (floor || (prm->stop_rule == 1 && eps < prm->tol)) return promote(in);
-        } else if (in.dc && fp32_phase) {
-            // hand over once the FP32 iterate meets the stop rule (FP64 confirms
-            // it) or sits at its rounding floor.  eps_q < tol near the floor at
-            // a check without a new minimum of r is either stagnation or a noisy
-            // but converging r (a 512^3 foam along x ran 304,200 sweeps where y
-            // and z met the rule at 160,000): the FP32 phase ends either way, as
-            // at the floor, and s0 + e must meet the rule again
-            if (met_dc) return promote(in);
-            if (floor || (prm->stop_rule == 1 && eps < prm->tol)) {
-                if (prm->dc_form == 1) return promote(in);
-                in.to_delta = true;  // after this round of checks: it launches a sweep
-                return PM_OK;
-            }
-        } else if (met) {
+        // the plateau test keeps a count across checks: run it only where the
+        // floor decision reads it
+        const bool plateau = fp32_phase && near_floor && in.stall < 5 && at_fp32_floor(in);
+        CheckState c;
+        c.dc = in.dc;
+        c.fp32_phase = fp32_phase;
+        c.delta = in.delta;
+        c.stop_rule = prm->stop_rule;
+        c.dc_form = prm->dc_form;
+        c.tol = prm->tol;
+        c.r = r;
+        c.eps = eps;
+        c.near_floor = near_floor;
+        c.stall = in.stall;
+        c.plateau = plateau;
+        c.budget_spent = in.sweeps >= prm->max_sweeps;
+        switch (decide(c)) {
+        case CheckAction::Stop:
             in.status = PM_OK;
             return finalize(in);
-        }
-        if (!in.dc && floor) {
-            in.status = PM_NOT_CONVERGED;  // FP32 rounding floor above tol
-            return finalize(in);
-        }
-        if (in.sweeps >= prm->max_sweeps) {
+        case CheckAction::NotConverged:
             in.status = PM_NOT_CONVERGED;
             return finalize(in);
+        case CheckAction::Promote:
+            return promote(in);
+        case CheckAction::ToCorrection:
+            in.to_delta = true;  // after this round of checks: it launches a sweep
+            return PM_OK;
+        case CheckAction::Continue:
+            break;
         }
         return PM_OK;
     }
