@@ -701,17 +701,23 @@ __device__ __forceinline__ void fused_chunk(FusedShared<T, TX, TY> &sh, const In
         T *const swn = sh.w[wn];
 
         // ---- stage plane zz (u, v, p) and plane zz + 1 (w)
-        su[cl] = Uw[2];
-        sv[cl] = Vw[2];
-        sp[cl] = pold;
-        swn[cl] = Ww[2];
-        if (has_halo) {
-            su[hlds] = hU;
-            sv[hlds] = hV;
-            swn[hlds] = hW;
-            if (has_ph) sp[hlds] = hP;
-        }
-
+        auto stage = [&]() __attribute__((always_inline)) {
+            su[cl] = Uw[2];
+            sv[cl] = Vw[2];
+            sp[cl] = pold;
+            swn[cl] = Ww[2];
+            if (has_halo) {
+                su[hlds] = hU;
+                sv[hlds] = hV;
+                swn[hlds] = hW;
+                if (has_ph) sp[hlds] = hP;
+            }
+        };
+        // the prologue issues its loads before it stages the primed values, so
+        // that both sets of loads are in flight at once (a chunk of one plane:
+        // one memory round trip fewer, 32^3 solve 5.4 -> 5.2 us per sweep); in
+        // the loop the staging goes first (loads first measured 0.4 % slower)
+        if constexpr (body) stage();
         // ---- loads for iteration zz + 1 (planes wrap, so every address is
         // valid)
         T bU = T(0), bV = T(0), bW = T(0), bP = T(0);
@@ -739,6 +745,7 @@ __device__ __forceinline__ void fused_chunk(FusedShared<T, TX, TY> &sh, const In
             bhW = bload<T, LAUX>(rW2, hoff_b);
             if (has_ph) bhP = bload<T, LAUX>(rP1, hoff_b);
         }
+        if constexpr (!body) stage();
         __syncthreads();
 
         // ---- p^n of the own cell
