@@ -342,8 +342,13 @@ def series_workload(args) -> dict:
         desc = ("open-cell foam: 512^3 Voronoi-edge struts (200 seeds, radius 3, seed 4), 8 strain "
                 "states rescaled along z to 512..384 planes; 3 load axes; 24 instances batched, "
                 "autotuned decomposition")
-    if args.states > 0:
-        # the first states only (their instances keep the series' numbering)
+    index = list(range(len(states)))
+    if args.state_indices:
+        index = [int(x) for x in args.state_indices.split(",")]
+        states = [states[i] for i in index]
+        desc += f"; states {args.state_indices} only"
+    elif args.states > 0:
+        index = index[:args.states]
         states = states[:args.states]
         desc += f"; first {len(states)} state(s) only"
     masks = [ps.to_device(m) for m in states]
@@ -354,7 +359,7 @@ def series_workload(args) -> dict:
     pores = [ctx.pores(m, labels=False, flow=False) for m in masks]
     torch.cuda.synchronize()
     pores_s = time.perf_counter() - t0
-    pore_info = [{"state": i, "components": p["n_components"], "percolates": list(p["percolates"]),
+    pore_info = [{"state": index[i], "components": p["n_components"], "percolates": list(p["percolates"]),
                   "flowing_fraction": [round(p["n_flowing"][j] / max(p["n_pore"], 1), 4) for j in range(3)]}
                  for i, p in enumerate(pores)]
     log(f"[bench] pore connectivity of {len(masks)} states: {pores_s:.2f} s")
@@ -369,7 +374,7 @@ def series_workload(args) -> dict:
         for i, m in enumerate(masks):
             for pr in (ps.FP32, ps.FP64):
                 best = ctx.autotune(m, pr)
-                log(f"[bench] autotuned state {i} {tuple(m.shape)} {'fp32' if pr == ps.FP32 else 'fp64'}: {best}")
+                log(f"[bench] autotuned state {index[i]} {tuple(m.shape)} {'fp32' if pr == ps.FP32 else 'fp64'}: {best}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     status, res = ctx.solve_batch(probs, prm)
@@ -377,7 +382,7 @@ def series_workload(args) -> dict:
     wall = time.perf_counter() - t0
     st = ctx.last_stats()
     vox = sum(int(states[i // len(axes)].size) * r["sweeps"] for i, r in enumerate(res))
-    inst = [{"state": i // len(axes), "axis": axes[i % len(axes)], "status": r["status"],
+    inst = [{"state": index[i // len(axes)], "axis": axes[i % len(axes)], "status": r["status"],
              "sweeps": r["sweeps"], "r_last": float(r["r"][-1]) if len(r["r"]) else None,
              "eps_q_last": float(r["eps"][-1]) if len(r["eps"]) else None,
              "k_col": [float(f"{x:.8g}") for x in r["kcol"]]} for i, r in enumerate(res)]
@@ -450,6 +455,8 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=0.0,
                     help="series workloads: tolerance of --stop-rule (0: its default)")
     ap.add_argument("--states", type=int, default=0, help="series workloads: solve only the first N states (0: all)")
+    ap.add_argument("--state-indices", default="",
+                    help="series workloads: solve only these states, e.g. 0,7 (overrides --states)")
     ap.add_argument("--pore-cleanup", type=int, choices=[0, 1], default=0,
                     help="series workloads: sweep only the pore components that percolate along the load axis")
     ap.add_argument("--calibrate-copy", action="store_true",
