@@ -180,7 +180,72 @@ int main()
         c.stall = 30;
         ok &= expect("promoted: no floor in FP64", c, CheckAction::Continue);
     }
+    // ---- invariants over every combination of flags, counts and levels
+    int combos = 0;
+    const int stalls[] = {0, 1, 4, 5, 19, 20};
+    const double rs[] = {0.5e-8, 1e-3};                       // below / above tol 1e-8 (rule 0)
+    const double epss[] = {0.0, 0.5e-6, 2e-6, INFINITY};       // against tol 1e-6 (rule 1)
+    for (int bits = 0; bits < 64; ++bits)
+        for (int rule = 0; rule < 2; ++rule)
+            for (int form = 0; form < 2; ++form)
+                for (int st : stalls)
+                    for (double r : rs)
+                        for (double e : epss) {
+                            CheckState c{};
+                            c.dc = bits & 1;
+                            c.fp32_phase = bits & 2;
+                            c.delta = bits & 4;
+                            c.near_floor = bits & 8;
+                            c.plateau = bits & 16;
+                            c.budget_spent = bits & 32;
+                            if (c.delta && !(c.dc && c.fp32_phase)) continue;  // no such state
+                            c.stop_rule = rule;
+                            c.dc_form = form;
+                            c.tol = rule == 0 ? 1e-8 : 1e-6;
+                            c.stall = st;
+                            c.r = r;
+                            c.eps = e;
+                            ++combos;
+                            const CheckAction a = ps::decide(c);
+                            const bool rule_met = rule == 0 ? r < c.tol : e < c.tol;
+                            bool good = true;
+                            // a spent budget ends the solve or its phase
+                            good &= !(c.budget_spent && a == CheckAction::Continue);
+                            // Stop only where the rule holds; in single precision
+                            // under eps_q never near the floor; never from the FP32
+                            // phase of FP32-DC, which a later phase must confirm
+                            if (a == CheckAction::Stop) {
+                                good &= rule_met;
+                                good &= !(rule == 1 && c.fp32_phase && c.near_floor);
+                                good &= !(c.dc && c.fp32_phase && !c.delta);
+                            }
+                            // phase changes only from single precision under FP32-DC;
+                            // the correction form only from the FP32 phase, dc_form 0
+                            if (a == CheckAction::Promote) good &= c.dc && c.fp32_phase;
+                            if (a == CheckAction::ToCorrection)
+                                good &= c.dc && c.fp32_phase && !c.delta && form == 0;
+                            // FP64 ignores the floor signals
+                            if (!c.fp32_phase) {
+                                CheckState d = c;
+                                d.near_floor = !c.near_floor;
+                                d.plateau = !c.plateau;
+                                d.stall = c.stall == 0 ? 20 : 0;
+                                good &= ps::decide(d) == a;
+                            }
+                            // in single precision, eps_q < tol always ends the phase
+                            // under FP32-DC
+                            if (c.dc && c.fp32_phase && rule == 1 && e < c.tol)
+                                good &= a == CheckAction::Stop || a == CheckAction::Promote ||
+                                        a == CheckAction::ToCorrection;
+                            if (!good) {
+                                std::printf("invariant broken: dc %d fp32 %d delta %d near %d plateau %d budget %d "
+                                            "rule %d form %d stall %d r %g eps %g -> %s\n",
+                                            c.dc, c.fp32_phase, c.delta, c.near_floor, c.plateau, c.budget_spent,
+                                            rule, form, st, r, e, name(a));
+                                ok = false;
+                            }
+                        }
     if (!ok) return 1;
-    std::printf("ok %d\n", cases);
+    std::printf("ok %d %d\n", cases, combos);
     return 0;
 }
