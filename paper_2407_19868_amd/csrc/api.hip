@@ -1160,24 +1160,11 @@ struct Engine {
         return PM_OK;
     }
 
-    // FP32 rounding floor reached?  With r_n ~ r_inf + C rho^n, Aitken's
-    // extrapolation of three residuals K checks apart estimates r_inf; the
-    // iterate is at its floor once most of r is that limit (or r stopped
-    // falling).  Multi-rate decay can fool one estimate, so two consecutive
-    // hits are required.
+    // FP32 rounding floor reached?  Two consecutive hits of the plateau
+    // reading (csrc/stopping.h) on the phase's residual history.
     bool at_fp32_floor(Inst &in) const
     {
-        const std::vector<double> &h = in.rphase;
-        const size_t K = 5, n = h.size();
-        if (n < 2 * K + 1) return false;
-        const double a = h[n - 1 - 2 * K], b = h[n - 1 - K], c = h[n - 1];
-        bool hit;
-        if (!(b < a) || !(c < b)) {
-            hit = true;  // no progress over K checks
-        } else {
-            const double d1 = b - a, d2 = c - b, den = d2 - d1;
-            hit = den > 0 && (c - d2 * d2 / den) > 0.8 * c;
-        }
+        const bool hit = plateau_reading(in.rphase.data(), in.rphase.size());
         in.plateau_hits = hit ? in.plateau_hits + 1 : 0;
         return in.plateau_hits >= 2;
     }

@@ -7,7 +7,24 @@
 // eps_q < tol, the criterion of the paper's large-domain runs (§7.1).
 #pragma once
 
+#include <cstddef>
+
 namespace ps {
+
+// One reading of the FP32 floor's plateau test on a phase's residual history
+// h[0..n).  With r_n ~ r_inf + C rho^n, Aitken's extrapolation of three
+// residuals K checks apart estimates r_inf: the reading is a hit once most of
+// the current r is that limit (above 0.8 of it), or when r did not fall over
+// either K-check span.  Multi-rate decay can fool one estimate, so the engine
+// asks for two consecutive hits.
+inline bool plateau_reading(const double *h, size_t n, size_t K = 5)
+{
+    if (n < 2 * K + 1) return false;
+    const double a = h[n - 1 - 2 * K], b = h[n - 1 - K], c = h[n - 1];
+    if (!(b < a) || !(c < b)) return true;  // no progress over K checks
+    const double d1 = b - a, d2 = c - b, den = d2 - d1;
+    return den > 0 && (c - d2 * d2 / den) > 0.8 * c;
+}
 
 enum class CheckAction {
     Continue,      // sweep on

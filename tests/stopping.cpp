@@ -44,9 +44,40 @@ static bool expect(const char *what, const CheckState &c, CheckAction want)
     return true;
 }
 
+static bool expect_reading(const char *what, const double *h, size_t n, bool want)
+{
+    ++cases;
+    const bool got = ps::plateau_reading(h, n);
+    if (got != want) {
+        std::printf("%s: reading %d, want %d\n", what, got, want);
+        return false;
+    }
+    return true;
+}
+
 int main()
 {
     bool ok = true;
+    // ---- plateau reading of the residual history (K = 5: checks n-11, n-6, n-1)
+    {
+        double h[31];
+        for (int k = 0; k < 31; ++k) h[k] = std::pow(0.9, k);
+        ok &= expect_reading("ten checks are too few", h, 10, false);
+        ok &= expect_reading("geometric decay to zero", h, 11, false);
+        ok &= expect_reading("geometric decay to zero, late", h, 31, false);
+        for (int k = 0; k < 31; ++k) h[k] = 1e-3 + 1e-3 * std::pow(0.9, k);
+        ok &= expect_reading("decay onto a floor, early (limit below 0.8 r)", h, 11, false);
+        ok &= expect_reading("decay onto a floor, late (limit above 0.8 r)", h, 31, true);
+        for (int k = 0; k < 31; ++k) h[k] = 2e-5;
+        ok &= expect_reading("flat", h, 31, true);
+        for (int k = 0; k < 31; ++k) h[k] = 1e-5 * (1.0 + 0.01 * k);
+        ok &= expect_reading("rising", h, 31, true);
+        for (int k = 0; k < 31; ++k) h[k] = std::pow(0.9, k);
+        h[30] = 1.05 * h[25];
+        ok &= expect_reading("last check above the one K before", h, 31, true);
+        h[30] = 0.95 * h[25];
+        ok &= expect_reading("decay that slows sharply over the last K checks", h, 31, true);
+    }
     // ---- FP64: the rule as written, no floor gate
     {
         CheckState c = base();
